@@ -1,0 +1,719 @@
+// Host side of the C ABI (include/sivf.h): context and workspace management,
+// input validation, and the sequencing of the assignment step (Alg. 4),
+// update step (Alg. 5) and Lloyd driver (Alg. 1) on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sivf;
+
+namespace {
+
+sivf_status fail(sivf_ctx* ctx, sivf_status st, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), SIVF_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                       \
+    } while (0)
+
+#define STCHK(expr)                      \
+    do {                                 \
+        sivf_status s_ = (expr);         \
+        if (s_ != SIVF_OK) return s_;    \
+    } while (0)
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool cap_ok(sivf_ctx* ctx, size_t more) {
+    return ctx->opt.workspace_cap_bytes == 0 || ctx->bytes_held + more <= ctx->opt.workspace_cap_bytes;
+}
+
+sivf_status dev_alloc(sivf_ctx* ctx, void** p, size_t bytes, size_t* account) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (!cap_ok(ctx, bytes))
+        return fail(ctx, SIVF_E_NOMEM, "workspace cap of %zu bytes exceeded (%zu held, %zu requested)",
+                    ctx->opt.workspace_cap_bytes, ctx->bytes_held, bytes);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(ctx, SIVF_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    ctx->bytes_held += bytes;
+    if (account) *account += bytes;
+    return SIVF_OK;
+}
+
+void dev_free(sivf_ctx* ctx, void* p, size_t bytes, size_t* account) {
+    if (!p) return;
+    if (bytes == 0) bytes = 8;
+    (void)hipFree(p);
+    ctx->bytes_held -= std::min(ctx->bytes_held, bytes);
+    if (account) *account -= std::min(*account, bytes);
+}
+
+// Grow-only named workspace buffer owned by the ctx.
+template <typename T>
+sivf_status ws(sivf_ctx* ctx, const char* name, int64_t elems, T** out) {
+    size_t bytes = (size_t)std::max<int64_t>(elems, 1) * sizeof(T);
+    auto it = ctx->ws.find(name);
+    if (it != ctx->ws.end() && it->second.second >= bytes) {
+        *out = (T*)it->second.first;
+        return SIVF_OK;
+    }
+    if (it != ctx->ws.end()) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        dev_free(ctx, it->second.first, it->second.second, nullptr);
+        ctx->ws.erase(it);
+    }
+    size_t grow = bytes + bytes / 8;
+    void* p = nullptr;
+    STCHK(dev_alloc(ctx, &p, grow, nullptr));
+    ctx->ws[name] = {p, grow};
+    *out = (T*)p;
+    return SIVF_OK;
+}
+
+sivf_status check_csr_args(sivf_ctx* ctx, const sivf_csr* X, const char* what) {
+    if (!X) return fail(ctx, SIVF_E_INVALID, "%s is NULL", what);
+    if (X->n_rows < 0 || X->n_cols < 1 || X->nnz < 0)
+        return fail(ctx, SIVF_E_SHAPE, "%s: bad sizes n_rows=%lld n_cols=%lld nnz=%lld", what, (long long)X->n_rows,
+                    (long long)X->n_cols, (long long)X->nnz);
+    if (X->n_cols > INT32_MAX) return fail(ctx, SIVF_E_SHAPE, "%s: n_cols exceeds int32", what);
+    if (!X->row_ptr || (X->nnz > 0 && (!X->col || !X->val)))
+        return fail(ctx, SIVF_E_INVALID, "%s: NULL array", what);
+    if (X->val_dtype != SIVF_F32 && X->val_dtype != SIVF_F64)
+        return fail(ctx, SIVF_E_INVALID, "%s: values must be SIVF_F32 or SIVF_F64", what);
+    return SIVF_OK;
+}
+
+sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out, bool force) {
+    STCHK(check_csr_args(ctx, X, "X"));
+    const int f64 = X->val_dtype == SIVF_F64;
+    const bool same = ctx->vx_rp == X->row_ptr && ctx->vx_col == X->col && ctx->vx_val == X->val &&
+                      ctx->vx_n == X->n_rows && ctx->vx_d == X->n_cols && ctx->vx_nnz == X->nnz &&
+                      ctx->vx_f64 == f64;
+    if (!same || force) {
+        unsigned long long* flags = nullptr;
+        STCHK(ws(ctx, "vflags", 4, &flags));
+        unsigned long long init[3] = {0ull, ~0ull, 0ull};
+        HIPCHK(ctx, hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+        if (X->n_rows > 0)
+            HIPCHK(ctx, validate_csr(X->row_ptr, X->col, X->val, f64, X->n_rows, X->n_cols, X->nnz, flags, ctx->stream));
+        unsigned long long h[3];
+        HIPCHK(ctx, hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (X->n_rows == 0) {
+            int64_t rp0 = 0;
+            HIPCHK(ctx, hipMemcpy(&rp0, X->row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost));
+            if (rp0 != 0 || X->nnz != 0) return fail(ctx, SIVF_E_UNSORTED, "X: empty matrix with row_ptr[0] != 0 or nnz != 0");
+        }
+        if (h[0] & 1ull) return fail(ctx, SIVF_E_UNSORTED, "X: row %llu has unsorted/duplicate columns or a decreasing row_ptr", h[1]);
+        if (h[0] & 8ull) return fail(ctx, SIVF_E_UNSORTED, "X: row_ptr[0] != 0 or row_ptr[n] != nnz");
+        if (h[0] & 2ull) return fail(ctx, SIVF_E_RANGE, "X: row %llu has a column outside [0, %lld)", h[1], (long long)X->n_cols);
+        if (h[0] & 4ull) return fail(ctx, SIVF_E_NONFINITE, "X: row %llu has a non-finite value", h[1]);
+        ctx->vx_rp = X->row_ptr;
+        ctx->vx_col = X->col;
+        ctx->vx_val = X->val;
+        ctx->vx_n = X->n_rows;
+        ctx->vx_d = X->n_cols;
+        ctx->vx_nnz = X->nnz;
+        ctx->vx_f64 = f64;
+        ctx->vx_nonneg = h[2] ? 0 : 1;
+    }
+    out->n = X->n_rows;
+    out->d = X->n_cols;
+    out->nnz = X->nnz;
+    out->rp = X->row_ptr;
+    out->col = X->col;
+    out->val = X->val;
+    out->f64 = f64;
+    out->nonneg = ctx->vx_nonneg;
+    return SIVF_OK;
+}
+
+// Every a[i] must lie in [0, k) before it is used as an index on the device.
+sivf_status check_assign(sivf_ctx* ctx, const int32_t* a, int64_t n, int32_t k, const char* what) {
+    if (n <= 0) return SIVF_OK;
+    unsigned long long* flags = nullptr;
+    STCHK(ws(ctx, "aflags", 2, &flags));
+    HIPCHK(ctx, fill_u64(flags, 0ull, 1, ctx->stream));
+    HIPCHK(ctx, range_check_i32(a, n, k, flags, ctx->stream));
+    unsigned long long h = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&h, flags, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (h) return fail(ctx, SIVF_E_RANGE, "%s has a value outside [0, %d)", what, k);
+    return SIVF_OK;
+}
+
+void choose_tiles(const sivf_ctx* ctx, int32_t k, int32_t* kt, int32_t* T) {
+    int32_t want = ctx->opt.k_tile;
+    if (want <= 0) {
+        const int32_t kmax = 2048;
+        int32_t t = (k + kmax - 1) / kmax;
+        int32_t w = (k + t - 1) / t;
+        want = ((w + 63) / 64) * 64;
+    }
+    *kt = want;
+    *T = (k + want - 1) / want;
+}
+
+// ---------------------------------------------------------------- file storage
+sivf_status store_reserve(sivf_ctx* ctx, sivf_ivf* f, Store* st, int64_t cap) {
+    if (st->cap >= cap && st->term) return SIVF_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, st->term, (size_t)st->cap * sizeof(int32_t), &f->bytes);
+    dev_free(ctx, st->val, (size_t)st->cap * sizeof(double), &f->bytes);
+    st->term = nullptr;
+    st->val = nullptr;
+    st->cap = 0;
+    int64_t c = std::max<int64_t>(cap + cap / 8, 64);
+    STCHK(dev_alloc(ctx, (void**)&st->term, (size_t)c * sizeof(int32_t), &f->bytes));
+    STCHK(dev_alloc(ctx, (void**)&st->val, (size_t)c * sizeof(double), &f->bytes));
+    st->cap = c;
+    return SIVF_OK;
+}
+
+sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
+    if (f->pcap >= P && f->cid) return SIVF_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, f->cid, (size_t)f->pcap * 2, &f->bytes);
+    dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
+    dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
+    dev_free(ctx, f->v64, (size_t)f->pcap * 8, &f->bytes);
+    f->cid = nullptr;
+    f->v32 = nullptr;
+    f->v16 = nullptr;
+    f->v64 = nullptr;
+    f->pcap = 0;
+    int64_t c = std::max<int64_t>(P + P / 8, 64);
+    STCHK(dev_alloc(ctx, (void**)&f->cid, (size_t)c * 2, &f->bytes));
+    if (f->pdt == SIVF_BF16) {
+        STCHK(dev_alloc(ctx, (void**)&f->v16, (size_t)c * 2, &f->bytes));
+    } else {
+        STCHK(dev_alloc(ctx, (void**)&f->v32, (size_t)c * 4, &f->bytes));
+    }
+    STCHK(dev_alloc(ctx, (void**)&f->v64, (size_t)c * 8, &f->bytes));
+    f->pcap = c;
+    return SIVF_OK;
+}
+
+void free_file(sivf_ctx* ctx, sivf_ivf* f) {
+    if (!f) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    Store* sts[2] = {&f->cur, &f->nxt};
+    for (Store* st : sts) {
+        dev_free(ctx, st->start, (size_t)f->k * 8, &f->bytes);
+        dev_free(ctx, st->nnz, (size_t)f->k * 8, &f->bytes);
+        dev_free(ctx, st->term, (size_t)st->cap * 4, &f->bytes);
+        dev_free(ctx, st->val, (size_t)st->cap * 8, &f->bytes);
+    }
+    dev_free(ctx, f->seg, (size_t)(f->d * f->T + 1) * 8, &f->bytes);
+    dev_free(ctx, f->mid, (size_t)(f->d * f->T) * 4, &f->bytes);
+    dev_free(ctx, f->cid, (size_t)f->pcap * 2, &f->bytes);
+    dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
+    dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
+    dev_free(ctx, f->v64, (size_t)f->pcap * 8, &f->bytes);
+    dev_free(ctx, f->lam, (size_t)f->k, &f->bytes);
+    dev_free(ctx, f->cnorm, (size_t)f->k * 8, &f->bytes);
+    delete f;
+}
+
+sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
+    sivf_ivf* f = new (std::nothrow) sivf_ivf();
+    if (!f) return fail(ctx, SIVF_E_NOMEM, "host allocation failed");
+    f->k = k;
+    f->d = d;
+    f->pdt = ctx->opt.posting_dtype;
+    choose_tiles(ctx, k, &f->kt, &f->T);
+    sivf_status st = SIVF_OK;
+    for (Store* s : {&f->cur, &f->nxt}) {
+        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&s->start, (size_t)k * 8, &f->bytes);
+        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&s->nnz, (size_t)k * 8, &f->bytes);
+    }
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->seg, (size_t)(d * f->T + 1) * 8, &f->bytes);
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mid, (size_t)(d * f->T) * 4, &f->bytes);
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->lam, (size_t)k, &f->bytes);
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->cnorm, (size_t)k * 8, &f->bytes);
+    if (st != SIVF_OK) {
+        free_file(ctx, f);
+        return st;
+    }
+    *out = f;
+    return SIVF_OK;
+}
+
+// Structure f's current centroids by the flags in f->lam (Alg. 5 second half).
+sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
+    const int64_t W64 = ivf_w64(f->k);
+    const int64_t nseg2 = f->d * f->T * 2;
+    IvfBuildWs w{};
+    STCHK(ws(ctx, "ivf_bm", W64 * f->d, &w.bm));
+    STCHK(ws(ctx, "ivf_lbits", W64, &w.lbits));
+    STCHK(ws(ctx, "ivf_pre0", W64 * f->d, &w.pre0));
+    STCHK(ws(ctx, "ivf_pre1", W64 * f->d, &w.pre1));
+    STCHK(ws(ctx, "ivf_cnt", nseg2, &w.cnt));
+    STCHK(ws(ctx, "ivf_off", nseg2 + 1, &w.off));
+    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(std::max<int64_t>(nseg2, f->k + 1), ctx->vx_n + 1)) + 8,
+             &w.scan_ws));
+    HIPCHK(ctx, ivf_count(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, ctx->stream));
+    HIPCHK(ctx, ivf_offsets(f->d, f->T, w, f->seg, f->mid, ctx->stream));
+    int64_t P = 0, total = 0;
+    int64_t* cscan = nullptr;
+    STCHK(ws(ctx, "ivf_cscan", (int64_t)f->k + 1, &cscan));
+    HIPCHK(ctx, exclusive_scan_i64(f->cur.nnz, cscan, f->k, w.scan_ws, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&total, cscan + f->k, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&P, f->seg + f->d * f->T, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (P != total)
+        return fail(ctx, SIVF_E_HIP, "internal: %lld postings for %lld centroid entries", (long long)P, (long long)total);
+    STCHK(postings_reserve(ctx, f, P));
+    f->P = P;
+    HIPCHK(ctx, ivf_fill(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, f->cid, f->v32, f->v16, f->v64, ctx->stream));
+    if (!f->nonneg) HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
+    return SIVF_OK;
+}
+
+}  // namespace
+
+// =========================================================================== ABI
+extern "C" {
+
+sivf_status sivf_default_options(sivf_options* opt) {
+    if (!opt) return SIVF_E_INVALID;
+    opt->posting_dtype = SIVF_F32;
+    opt->filter_mode = SIVF_MODE_SIVF;
+    opt->k_tile = 0;
+    opt->certify = 1;
+    opt->workspace_cap_bytes = 0;
+    return SIVF_OK;
+}
+
+sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf_options* opt) {
+    if (!out) return SIVF_E_INVALID;
+    *out = nullptr;
+    sivf_options o;
+    sivf_default_options(&o);
+    if (opt) o = *opt;
+    if (o.posting_dtype != SIVF_F32 && o.posting_dtype != SIVF_BF16) return SIVF_E_INVALID;
+    if (o.filter_mode < 0 || o.filter_mode > 2) return SIVF_E_INVALID;
+    if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
+    sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
+    if (!ctx) return SIVF_E_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->opt = o;
+    DevGuard g(device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        ctx->n_cu = ncu;
+    for (auto& e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete ctx;
+            return SIVF_E_HIP;
+        }
+    }
+    *out = ctx;
+    return SIVF_OK;
+}
+
+sivf_status sivf_destroy(sivf_ctx* ctx) {
+    if (!ctx) return SIVF_OK;
+    DevGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->ws) (void)hipFree(kv.second.first);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return SIVF_OK;
+}
+
+const char* sivf_last_error(const sivf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+sivf_status sivf_validate_csr(sivf_ctx* ctx, const sivf_csr* X) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    Csr c;
+    return validate(ctx, X, &c, true);
+}
+
+sivf_status sivf_init_centroids(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const int32_t* init_ids_host,
+                                sivf_ivf** out) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!out || !init_ids_host) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, false));
+    if (k < 1 || k > Xc.n) return fail(ctx, SIVF_E_SHAPE, "need 1 <= k <= N (k=%d, N=%lld)", k, (long long)Xc.n);
+    for (int32_t j = 0; j < k; ++j)
+        if (init_ids_host[j] < 0 || init_ids_host[j] >= Xc.n)
+            return fail(ctx, SIVF_E_RANGE, "init id %d at position %d outside [0, N)", init_ids_host[j], j);
+    sivf_ivf* f = nullptr;
+    STCHK(new_file(ctx, k, Xc.d, &f));
+    f->nonneg = Xc.nonneg;
+    sivf_status st = SIVF_OK;
+    int32_t* ids = nullptr;
+    int64_t *lens = nullptr, *scan = nullptr, *sws = nullptr;
+    if (st == SIVF_OK) st = ws(ctx, "init_ids", k, &ids);
+    if (st == SIVF_OK) st = ws(ctx, "init_lens", k, &lens);
+    if (st == SIVF_OK) st = ws(ctx, "init_scan", k + 1, &scan);
+    if (st == SIVF_OK) st = ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(k + 1, Xc.n + 1)) + 8, &sws);
+    int64_t total = 0;
+    auto H = [&](hipError_t e) {
+        if (st == SIVF_OK && e != hipSuccess) st = fail(ctx, SIVF_E_HIP, "HIP error: %s", hipGetErrorString(e));
+    };
+    if (st == SIVF_OK) {
+        H(hipMemcpyAsync(ids, init_ids_host, (size_t)k * 4, hipMemcpyHostToDevice, ctx->stream));
+        H(gather_rows(Xc, ids, k, f->cur, lens, ctx->stream, 0));
+        H(exclusive_scan_i64(lens, scan, k, sws, ctx->stream));
+        H(hipMemcpyAsync(&total, scan + k, 8, hipMemcpyDeviceToHost, ctx->stream));
+        H(hipStreamSynchronize(ctx->stream));
+    }
+    if (st == SIVF_OK) st = store_reserve(ctx, f, &f->cur, total);
+    if (st == SIVF_OK) {
+        H(hipMemcpyAsync(f->cur.start, scan, (size_t)k * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        H(gather_rows(Xc, ids, k, f->cur, lens, ctx->stream, 1));
+        H(fill_u8(f->lam, 0, k, ctx->stream));
+    }
+    if (st == SIVF_OK) st = restructure(ctx, f);
+    if (st == SIVF_OK) H(hipStreamSynchronize(ctx->stream));
+    if (st != SIVF_OK) {
+        free_file(ctx, f);
+        return st;
+    }
+    *out = f;
+    return SIVF_OK;
+}
+
+sivf_status sivf_build_centroid_ivf(sivf_ctx* ctx, const sivf_csr* C, const uint8_t* lambda, sivf_ivf** out) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!out) return fail(ctx, SIVF_E_INVALID, "NULL out");
+    STCHK(check_csr_args(ctx, C, "centroids"));
+    if (C->val_dtype != SIVF_F64) return fail(ctx, SIVF_E_INVALID, "centroid values must be SIVF_F64");
+    if (C->n_rows < 1 || C->n_rows > INT32_MAX) return fail(ctx, SIVF_E_SHAPE, "need 1 <= k <= 2^31-1");
+    // validate with the same kernel (does not disturb the X cache)
+    unsigned long long* flags = nullptr;
+    STCHK(ws(ctx, "vflags", 4, &flags));
+    unsigned long long init[3] = {0ull, ~0ull, 0ull};
+    HIPCHK(ctx, hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, validate_csr(C->row_ptr, C->col, C->val, 1, C->n_rows, C->n_cols, C->nnz, flags, ctx->stream));
+    unsigned long long h[3];
+    HIPCHK(ctx, hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (h[0] & 9ull) return fail(ctx, SIVF_E_UNSORTED, "centroids: row %llu unsorted or bad row_ptr", h[1]);
+    if (h[0] & 2ull) return fail(ctx, SIVF_E_RANGE, "centroids: column out of range in row %llu", h[1]);
+    if (h[0] & 4ull) return fail(ctx, SIVF_E_NONFINITE, "centroids: non-finite value in row %llu", h[1]);
+    const int32_t k = (int32_t)C->n_rows;
+    sivf_ivf* f = nullptr;
+    STCHK(new_file(ctx, k, C->n_cols, &f));
+    f->nonneg = h[2] ? 0 : 1;
+    sivf_status st = store_reserve(ctx, f, &f->cur, C->nnz);
+    if (st == SIVF_OK) {
+        hipError_t e = csr_to_store(C->row_ptr, C->col, (const double*)C->val, k, f->cur, ctx->stream);
+        if (e == hipSuccess)
+            e = lambda ? hipMemcpyAsync(f->lam, lambda, (size_t)k, hipMemcpyDeviceToDevice, ctx->stream)
+                       : fill_u8(f->lam, 0, k, ctx->stream);
+        if (e != hipSuccess) st = fail(ctx, SIVF_E_HIP, "HIP error: %s", hipGetErrorString(e));
+    }
+    if (st == SIVF_OK) st = restructure(ctx, f);
+    if (st == SIVF_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(ctx, SIVF_E_HIP, "sync failed");
+    if (st != SIVF_OK) {
+        free_file(ctx, f);
+        return st;
+    }
+    *out = f;
+    return SIVF_OK;
+}
+
+sivf_status sivf_ivf_free(sivf_ctx* ctx, sivf_ivf* ivf) {
+    if (!ivf) return SIVF_OK;
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    free_file(ctx, ivf);
+    return SIVF_OK;
+}
+
+sivf_status sivf_ivf_sizes(sivf_ctx* ctx, const sivf_ivf* f, int32_t* k_host, int64_t* d_host, int64_t* nnz_host,
+                           int32_t* n_tiles_host, int32_t* k_tile_host) {
+    if (!ctx || !f) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (k_host) *k_host = f->k;
+    if (d_host) *d_host = f->d;
+    if (nnz_host) *nnz_host = f->P;
+    if (n_tiles_host) *n_tiles_host = f->T;
+    if (k_tile_host) *k_tile_host = f->kt;
+    return SIVF_OK;
+}
+
+sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* f, int64_t* c_ptr, int32_t* c_col, double* c_val,
+                            uint8_t* lambda, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val) {
+    if (!ctx || !f) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if ((c_col || c_val) && !c_ptr) return fail(ctx, SIVF_E_INVALID, "c_col/c_val need c_ptr");
+    if ((p_cid || p_val) && !term_ptr) return fail(ctx, SIVF_E_INVALID, "p_cid/p_val need term_ptr");
+    int64_t* sws = nullptr;
+    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(std::max<int64_t>(f->k, f->d) + 1, ctx->vx_n + 1)) + 8,
+             &sws));
+    if (c_ptr) {
+        HIPCHK(ctx, exclusive_scan_i64(f->cur.nnz, c_ptr, f->k, sws, ctx->stream));
+        if (c_col || c_val) HIPCHK(ctx, store_export(f->cur, f->k, c_ptr, c_col, c_val, ctx->stream));
+    }
+    if (lambda) HIPCHK(ctx, hipMemcpyAsync(lambda, f->lam, (size_t)f->k, hipMemcpyDeviceToDevice, ctx->stream));
+    if (term_ptr || split) {
+        int64_t* cnt = nullptr;
+        STCHK(ws(ctx, "exp_cnt", f->d, &cnt));
+        HIPCHK(ctx, ivf_export(f, term_ptr, split, p_cid, p_val, cnt, sws, ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SIVF_OK;
+}
+
+sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
+                        float* own_sim_inout, uint8_t* lambda_out, sivf_iter_stats* stats_host) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!f || !assign_inout || !own_sim_inout || !lambda_out) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    if (iter < 1) return fail(ctx, SIVF_E_INVALID, "iter must be >= 1");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, false));
+    if (Xc.d != f->d) return fail(ctx, SIVF_E_SHAPE, "X has %lld columns, centroids %lld", (long long)Xc.d, (long long)f->d);
+    const int64_t n = Xc.n;
+    const int32_t k = f->k;
+    const int icp_on = iter >= 2 && ctx->opt.filter_mode != SIVF_MODE_IVF;
+    if (iter >= 2) STCHK(check_assign(ctx, assign_inout, n, k, "assign_inout (a^[r-1])"));
+    const int64_t qcap = std::max<int64_t>(1024, n / 4);
+    unsigned long long* counters = nullptr;
+    int32_t *a_new = nullptr, *qobj = nullptr, *qcand = nullptr, *qcnt = nullptr, *fobj = nullptr;
+    float* own_new = nullptr;
+    uint8_t* changed = nullptr;
+    double *obj_partial = nullptr, *obj = nullptr;
+    const int nfin = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
+    STCHK(ws(ctx, "counters", 16, &counters));
+    STCHK(ws(ctx, "a_new", n, &a_new));
+    STCHK(ws(ctx, "own_new", n, &own_new));
+    STCHK(ws(ctx, "qobj", qcap, &qobj));
+    STCHK(ws(ctx, "qcand", qcap * kCandCap, &qcand));
+    STCHK(ws(ctx, "qcnt", qcap, &qcnt));
+    STCHK(ws(ctx, "fobj", std::max<int64_t>(n, 1), &fobj));
+    STCHK(ws(ctx, "changed", k, &changed));
+    STCHK(ws(ctx, "obj_partial", nfin + 1, &obj_partial));
+    STCHK(ws(ctx, "objective", 1, &obj));
+
+    WalkArgs A{};
+    A.n = n;
+    A.rp = Xc.rp;
+    A.col = Xc.col;
+    A.xval = Xc.val;
+    A.x_f64 = Xc.f64;
+    A.k = k;
+    A.kt = f->kt;
+    A.T = f->T;
+    A.seg = f->seg;
+    A.mid = f->mid;
+    A.cid = f->cid;
+    A.pval = f->pdt == SIVF_BF16 ? (const void*)f->v16 : (const void*)f->v32;
+    A.lam = f->lam;
+    A.cnorm = f->cnorm;
+    A.a_prev = assign_inout;
+    A.own_prev = own_sim_inout;
+    A.icp_on = icp_on;
+    A.cbicp = ctx->opt.filter_mode == SIVF_MODE_CBICP;
+    A.nonneg = Xc.nonneg && f->nonneg;
+    A.certify = ctx->opt.certify;
+    A.eta_val = f->pdt == SIVF_BF16 ? (0x1p-8 + 0x1p-24 + 0x1p-32) : 0x1p-24;
+    A.eta_x = Xc.f64 ? 0x1p-24 : 0.0;
+    A.a_new = a_new;
+    A.own_new = own_new;
+    A.qobj = qobj;
+    A.qcand = qcand;
+    A.qcnt = qcnt;
+    A.fobj = fobj;
+    A.counters = counters;
+    A.qcap = qcap;
+
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, fill_u64(counters, 0ull, 16, s));
+    HIPCHK(ctx, fill_u8(changed, 0, k, s));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+    if (n > 0) {
+        const int bpc = walk_blocks_per_cu(f->kt, f->pdt == SIVF_BF16);
+        HIPCHK(ctx, walk_fast(A, f->pdt == SIVF_BF16, ctx->n_cu * bpc * kWalkWaves, s));
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    if (n > 0) {
+        HIPCHK(ctx, rescore_candidates(A, f->cur, (int64_t)ctx->n_cu * 16, s));
+        HIPCHK(ctx, rescore_full(A, f->v64, f->cur, (int64_t)ctx->n_cu * 4, s));
+        HIPCHK(ctx, finalize_assign(n, iter, a_new, own_new, assign_inout, own_sim_inout, changed, counters,
+                                    obj_partial, nfin, s));
+    }
+    HIPCHK(ctx, finalize_lambda(k, iter, changed, lambda_out, counters, obj_partial, n > 0 ? nfin : 0, obj, s));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    if (stats_host) {
+        unsigned long long c[8];
+        double o = 0.0;
+        HIPCHK(ctx, hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(&o, obj, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        memset(stats_host, 0, sizeof(*stats_host));
+        stats_host->iter = iter;
+        stats_host->multadds = (int64_t)c[0];
+        stats_host->rescored_objects = (int64_t)std::min<unsigned long long>(c[1], (unsigned long long)qcap);
+        stats_host->full_rescored = (int64_t)c[2];
+        stats_host->icp_objects = (int64_t)c[3];
+        stats_host->rescored_candidates = (int64_t)c[4];
+        stats_host->moved = (int64_t)c[5];
+        stats_host->n_invariant = (int32_t)c[6];
+        stats_host->objective_fast = o;
+        float t = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+        stats_host->t_walk_ms = t;
+        HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[2]));
+        stats_host->t_assign_ms = t;
+    }
+    return SIVF_OK;
+}
+
+sivf_status sivf_update(sivf_ctx* ctx, const sivf_csr* X, const int32_t* assign, const uint8_t* lambda,
+                        sivf_ivf* f, sivf_iter_stats* stats_host) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!f || !assign || !lambda) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, false));
+    if (Xc.d != f->d) return fail(ctx, SIVF_E_SHAPE, "X has %lld columns, centroids %lld", (long long)Xc.d, (long long)f->d);
+    const int64_t n = Xc.n;
+    const int32_t k = f->k;
+    hipStream_t s = ctx->stream;
+    UpdateWs w{};
+    w.nblk = std::max<int64_t>(1, (n + kObjBlock - 1) / kObjBlock);
+    w.nslots = ctx->n_cu * 8;
+    STCHK(ws(ctx, "u_hist", w.nblk * (int64_t)k, &w.hist));
+    STCHK(ws(ctx, "u_ccount", k, &w.ccount));
+    STCHK(ws(ctx, "u_cstart", k + 1, &w.cstart));
+    STCHK(ws(ctx, "u_perm", std::max<int64_t>(n, 1), &w.perm));
+    STCHK(ws(ctx, "u_memnnz", k, &w.memnnz));
+    STCHK(ws(ctx, "u_ub", k, &w.ub));
+    STCHK(ws(ctx, "u_ubscan", k + 1, &w.ubscan));
+    STCHK(ws(ctx, "u_work", 1, &w.work));
+    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(std::max<int64_t>(k, f->d * f->T * 2) + 1, n + 1)) + 8,
+             &w.scan_ws));
+    {
+        // the dense accumulators must start zeroed; the kernel keeps them zero
+        auto it = ctx->ws.find("u_W");
+        const size_t need = (size_t)w.nslots * (size_t)Xc.d * sizeof(double);
+        bool fresh = it == ctx->ws.end() || it->second.second < need;
+        STCHK(ws(ctx, "u_W", (int64_t)w.nslots * Xc.d, &w.W));
+        if (fresh) HIPCHK(ctx, fill_f64(w.W, 0.0, (int64_t)w.nslots * Xc.d, s));
+    }
+    STCHK(check_assign(ctx, assign, n, k, "assign"));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    HIPCHK(ctx, upd_sort(assign, n, k, Xc.rp, w, s));
+    HIPCHK(ctx, upd_bounds(k, Xc.d, lambda, 1, f->cur, w, s));
+    int64_t total = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&total, w.ubscan + k, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    STCHK(store_reserve(ctx, f, &f->nxt, total));
+    HIPCHK(ctx, upd_segsum(Xc, k, lambda, 1, f->cur, f->nxt, w, s));
+    std::swap(f->cur, f->nxt);
+    HIPCHK(ctx, hipMemcpyAsync(f->lam, lambda, (size_t)k, hipMemcpyDeviceToDevice, s));
+    f->nonneg = f->nonneg && Xc.nonneg;
+    STCHK(restructure(ctx, f));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[4], s));
+    if (stats_host) {
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        float t = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4]));
+        stats_host->t_update_ms = t;
+    }
+    return SIVF_OK;
+}
+
+sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const int32_t* init_ids_host, int32_t max_iter,
+                           int32_t* assign_out, float* own_sim_out, sivf_ivf** centroids_out,
+                           sivf_iter_stats* per_iter_host, int32_t* iters_done_host) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (max_iter < 1) return fail(ctx, SIVF_E_INVALID, "max_iter must be >= 1");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, false));
+    sivf_ivf* f = nullptr;
+    STCHK(sivf_init_centroids(ctx, X, k, init_ids_host, &f));
+    int32_t* a = assign_out;
+    float* own = own_sim_out;
+    uint8_t* lam = nullptr;
+    sivf_status st = SIVF_OK;
+    if (!a) st = ws(ctx, "lloyd_a", Xc.n, &a);
+    if (st == SIVF_OK && !own) st = ws(ctx, "lloyd_own", Xc.n, &own);
+    if (st == SIVF_OK) st = ws(ctx, "lloyd_lam", k, &lam);
+    int32_t done = 0;
+    for (int32_t r = 1; st == SIVF_OK && r <= max_iter; ++r) {
+        sivf_iter_stats stt{};
+        st = sivf_assign(ctx, X, f, r, a, own, lam, &stt);
+        if (st != SIVF_OK) break;
+        done = r;
+        if (per_iter_host) per_iter_host[r - 1] = stt;
+        if (r >= 2 && stt.moved == 0) break;
+        if (r == max_iter) break;  // the last assignment's centroids stay as they are
+        st = sivf_update(ctx, X, a, lam, f, &stt);
+        if (st != SIVF_OK) break;
+        if (per_iter_host) per_iter_host[r - 1].t_update_ms = stt.t_update_ms;
+    }
+    if (st == SIVF_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(ctx, SIVF_E_HIP, "sync failed");
+    if (iters_done_host) *iters_done_host = done;
+    if (st != SIVF_OK || !centroids_out) {
+        free_file(ctx, f);
+        if (centroids_out) *centroids_out = nullptr;
+        return st;
+    }
+    *centroids_out = f;
+    return SIVF_OK;
+}
+
+sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr*, const float*, int32_t, float, float*, double*) {
+    if (!ctx) return SIVF_E_INVALID;
+    return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment not built yet");
+}
+
+sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr*, const float*, int32_t, float, const float*, float,
+                                 float*, float*) {
+    if (!ctx) return SIVF_E_INVALID;
+    return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment not built yet");
+}
+
+}  // extern "C"

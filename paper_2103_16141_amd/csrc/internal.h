@@ -1,0 +1,192 @@
+// Internal declarations shared by the C-ABI host code and the HIP kernels of
+// libsivf.so.  Nothing here is part of the public ABI (include/sivf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+
+#include "../../include/sivf.h"
+
+namespace sivf {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kCandCap = 32;       // candidate-list capacity per object in the fast pass
+constexpr int kWalkWaves = 4;      // waves per workgroup in the walk kernels
+constexpr int kMaxTile = 4096;     // largest similarity tile (centroids) per wave
+
+// A device CSR that passed validation.
+struct Csr {
+    int64_t n = 0, d = 0, nnz = 0;
+    const int64_t* rp = nullptr;
+    const int32_t* col = nullptr;
+    const void* val = nullptr;
+    int f64 = 0;      // values are double (else float)
+    int nonneg = 0;   // every value >= 0
+};
+
+// FP64 centroid store in "padded CSR" form: centroid j's sorted (term, value)
+// entries live at [start[j], start[j] + nnz[j]) of term/val.
+struct Store {
+    int64_t* start = nullptr;
+    int64_t* nnz = nullptr;
+    int32_t* term = nullptr;
+    double* val = nullptr;
+    int64_t cap = 0;    // capacity of term/val
+};
+
+// Everything one launch of the fast walk needs (passed by value).
+struct WalkArgs {
+    int64_t n;
+    const int64_t* rp;
+    const int32_t* col;
+    const void* xval;
+    int x_f64;
+    int32_t k, kt, T;
+    const int64_t* seg;     // [d*T + 1] segment starts, segment (t, tile) = t*T + tile
+    const int32_t* mid;     // [d*T] moving-part length of each segment
+    const uint16_t* cid;    // tile-local centroid ids
+    const void* pval;       // f32 or bf16 posting values
+    const uint8_t* lam;     // flags the file is structured by (lambda^[r-1])
+    const double* cnorm;    // ||mu_j|| upper bounds (signed-data bound)
+    const int32_t* a_prev;  // a^[r-1]
+    const float* own_prev;  // own similarity written at r-1
+    int icp_on;             // iter >= 2 and filter mode uses ICP
+    int cbicp;              // ICP by per-posting test over whole lists
+    int nonneg;             // relative bound (X and centroids nonnegative)
+    int certify;
+    double eta_val;         // relative rounding of posting values
+    double eta_x;           // relative rounding of object values (f64 X -> f32)
+    // outputs
+    int32_t* a_new;
+    float* own_new;
+    int32_t* qobj;          // candidate re-score queue: object ids
+    int32_t* qcand;         // kCandCap candidates per queue slot
+    int32_t* qcnt;          // candidates per slot
+    int32_t* fobj;          // full re-score queue: object ids
+    unsigned long long* counters;  // [0] multadds [1] queue len [2] full len [3] icp objects
+                                   // [4] re-scored candidates [5] moved [6] invariant [8] work
+    int64_t qcap;           // capacity of the candidate queue
+};
+
+}  // namespace sivf
+
+struct sivf_ivf {
+    int32_t k = 0;
+    int64_t d = 0;
+    int32_t kt = 0, T = 0;
+    sivf_dtype pdt = SIVF_F32;
+    sivf::Store cur, nxt;           // current centroids, and the buffer the next update writes
+    int64_t* seg = nullptr;         // [d*T + 1]
+    int32_t* mid = nullptr;         // [d*T]
+    uint16_t* cid = nullptr;        // [pcap]
+    float* v32 = nullptr;           // [pcap] (posting dtype f32)
+    uint16_t* v16 = nullptr;        // [pcap] (posting dtype bf16)
+    double* v64 = nullptr;          // [pcap] FP64 values (exact re-score over whole lists)
+    int64_t P = 0, pcap = 0;
+    uint8_t* lam = nullptr;         // [k]
+    double* cnorm = nullptr;        // [k]
+    int nonneg = 1;
+    size_t bytes = 0;               // device bytes held (counted against the ctx cap)
+};
+
+struct sivf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sivf_options opt{};
+    std::string err;
+    int n_cu = 256;
+    size_t bytes_held = 0;
+    std::map<std::string, std::pair<void*, size_t>> ws;  // grow-only named workspace
+    // identity of the last X that passed validation
+    const void* vx_rp = nullptr;
+    const void* vx_col = nullptr;
+    const void* vx_val = nullptr;
+    int64_t vx_n = -1, vx_d = -1, vx_nnz = -1;
+    int vx_f64 = -1, vx_nonneg = 0;
+    hipEvent_t ev[8] = {};
+};
+
+namespace sivf {
+
+// ---- launchers (all enqueue on `s`) ----
+// generic
+hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* bsum_ws, hipStream_t s);
+int64_t scan_ws_elems(int64_t n);
+hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+hipError_t fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+hipError_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+// validation: flags[0] |= error bits, flags[1] = min bad row, flags[2] = any negative
+hipError_t validate_csr(const int64_t* rp, const int32_t* col, const void* val, int f64, int64_t n,
+                        int64_t d, int64_t nnz, unsigned long long* flags, hipStream_t s);
+
+// flags[0] |= 1 if some a[i] is outside [0, k)
+hipError_t range_check_i32(const int32_t* a, int64_t n, int32_t k, unsigned long long* flags, hipStream_t s);
+
+// centroid init: gather rows ids[j] of X into store (start must be exclusive scan of lengths)
+hipError_t gather_rows(const Csr& X, const int32_t* ids, int32_t k, Store st, int64_t* lens_out,
+                       hipStream_t s, int phase);
+hipError_t centroid_norms(const Store st, int32_t k, double* cnorm, hipStream_t s);
+hipError_t csr_to_store(const int64_t* ptr, const int32_t* col, const double* val, int32_t k,
+                        Store st, hipStream_t s);
+
+// structured inverted file
+struct IvfBuildWs {
+    unsigned long long* bm;     // [d * W64] centroid-presence bitmap per term
+    unsigned long long* lbits;  // [W64] flag bits
+    uint16_t* pre0;             // [d * W64] moving-bit prefix within tile
+    uint16_t* pre1;             // [d * W64] invariant-bit prefix within tile
+    int64_t* cnt;               // [d * T * 2] (term, tile, part) counts
+    int64_t* off;               // [d * T * 2 + 1] exclusive scan of cnt
+    int64_t* scan_ws;
+};
+int64_t ivf_w64(int32_t k);
+hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam,
+                     IvfBuildWs w, hipStream_t s);
+hipError_t ivf_offsets(int64_t d, int32_t T, IvfBuildWs w, int64_t* seg, int32_t* mid, hipStream_t s);
+hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam,
+                    IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s);
+hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val,
+                      int64_t* ws_counts, int64_t* scan_ws, hipStream_t s);
+hipError_t store_export(const Store st, int32_t k, const int64_t* c_ptr, int32_t* c_col, double* c_val,
+                        hipStream_t s);
+
+// assignment
+hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, hipStream_t s);
+int walk_blocks_per_cu(int kt, int pdt_bf16);
+hipError_t rescore_candidates(const WalkArgs& a, const Store st, int64_t grid_waves, hipStream_t s);
+hipError_t rescore_full(const WalkArgs& a, const double* v64, const Store st, int64_t grid, hipStream_t s);
+hipError_t finalize_assign(int64_t n, int iter, const int32_t* a_new, const float* own_new, int32_t* a_io,
+                           float* own_io, uint8_t* changed, unsigned long long* counters,
+                           double* obj_partial, int nblk, hipStream_t s);
+hipError_t finalize_lambda(int32_t k, int iter, const uint8_t* changed, uint8_t* lam_out,
+                           unsigned long long* counters, const double* obj_partial, int nblk,
+                           double* obj_out, hipStream_t s);
+
+// update
+struct UpdateWs {
+    int64_t* hist;      // [nblk * k] per object-block cluster counts -> offsets
+    int64_t* ccount;    // [k] cluster sizes
+    int64_t* cstart;    // [k + 1] exclusive scan of sizes
+    int32_t* perm;      // [n] objects sorted by cluster (ascending id inside)
+    int64_t* memnnz;    // [k] sum of member row lengths
+    int64_t* ub;        // [k] entry bound per cluster
+    int64_t* ubscan;    // [k + 1] exclusive scan of ub
+    double* W;          // [nslots * d] dense FP64 accumulators, kept zero between uses
+    int64_t* scan_ws;
+    unsigned long long* work; // [1] work counter for seg_sum
+    int nslots;
+    int64_t nblk;
+};
+constexpr int kObjBlock = 4096;
+hipError_t upd_sort(const int32_t* a, int64_t n, int32_t k, const int64_t* rp, UpdateWs w, hipStream_t s);
+hipError_t upd_bounds(int32_t k, int64_t d, const uint8_t* lam, int allow_copy, const Store prev, UpdateWs w,
+                      hipStream_t s);
+hipError_t upd_segsum(const Csr& X, int32_t k, const uint8_t* lam, int allow_copy, const Store prev,
+                      Store next, UpdateWs w, hipStream_t s);
+
+}  // namespace sivf

@@ -1,0 +1,203 @@
+// Structured inverted file of the centroids (Section 4; Alg. 5, "determine an
+// inverted-file structure" and "make structured inverted-file").
+//
+// Device layout (one list per term, split by centroid tile for the LDS-tiled
+// walk): postings are ordered by (term, tile, part, centroid id) where part 0
+// holds the moving centroids (flag 0) and part 1 the invariant ones.  With a
+// single tile this is exactly the paper's per-term [moving | invariant] list.
+//   seg[t*T + tile]  start of segment (t, tile); its end is seg[t*T + tile + 1]
+//   mid[t*T + tile]  length of the moving part of that segment
+//   cid[p]           centroid id minus tile*kt (16 bits)
+//   v32/v16[p]       posting value, RN to f32 (or RNE of that to bf16)
+//   v64[p]           the FP64 value (exact re-score over whole lists)
+//
+// Placement is deterministic without ordering atomics: a bitmap bm[w][t] marks
+// which centroids hold term t; the rank of centroid j inside its (t, tile,
+// part) segment is a popcount of lower bits, so every part comes out in
+// ascending centroid id regardless of thread timing (Alg. 5 fills in ascending
+// j the same way).
+#include "internal.h"
+#include "wave.h"
+
+namespace sivf {
+
+int64_t ivf_w64(int32_t k) { return ((int64_t)k + 63) / 64; }
+
+__global__ void k_ivf_bits(Store st, int32_t k, int64_t d, unsigned long long* __restrict__ bm) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < k; j += nw) {
+        const int64_t b = st.start[j], m = st.nnz[j];
+        unsigned long long* row = bm + (j >> 6) * d;
+        const unsigned long long bit = 1ull << (j & 63);
+        for (int64_t p = lane; p < m; p += 64) {
+            const int32_t t = st.term[b + p];
+            if (t >= 0 && t < d) atomicOr(&row[t], bit);
+        }
+    }
+}
+
+__global__ void k_lam_bits(const uint8_t* __restrict__ lam, int32_t k, unsigned long long* __restrict__ lbits) {
+    int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (w >= ((int64_t)k + 63) / 64) return;
+    unsigned long long m = 0;
+    for (int b = 0; b < 64; ++b) {
+        int64_t j = w * 64 + b;
+        if (j < k && lam && lam[j]) m |= 1ull << b;
+    }
+    lbits[w] = m;
+}
+
+// One thread per (tile, term): per-word prefix counts inside the tile and the
+// segment's part sizes.
+__global__ void k_ivf_counts(const unsigned long long* __restrict__ bm, const unsigned long long* __restrict__ lbits,
+                             int64_t d, int32_t kt, int32_t T, int64_t W64, uint16_t* __restrict__ pre0,
+                             uint16_t* __restrict__ pre1, int64_t* __restrict__ cnt) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= d * T) return;
+    const int64_t tile = idx / d, t = idx - tile * d;
+    const int64_t w0 = tile * (kt / 64);
+    int64_t w1 = w0 + kt / 64;
+    if (w1 > W64) w1 = W64;
+    uint32_t c0 = 0, c1 = 0;
+    for (int64_t w = w0; w < w1; ++w) {
+        unsigned long long m = bm[w * d + t];
+        unsigned long long lb = lbits[w];
+        pre0[w * d + t] = (uint16_t)c0;
+        pre1[w * d + t] = (uint16_t)c1;
+        c0 += __popcll(m & ~lb);
+        c1 += __popcll(m & lb);
+    }
+    cnt[(t * T + tile) * 2 + 0] = c0;
+    cnt[(t * T + tile) * 2 + 1] = c1;
+}
+
+hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam, IvfBuildWs w,
+                     hipStream_t s) {
+    const int64_t W64 = ivf_w64(k);
+    hipError_t e = fill_u64(w.bm, 0ull, W64 * d, s);
+    if (e != hipSuccess) return e;
+    int64_t blocks = ((int64_t)k * 64 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_ivf_bits, dim3((unsigned)blocks), dim3(256), 0, s, st, k, d, w.bm);
+    hipLaunchKernelGGL(k_lam_bits, dim3((unsigned)((W64 + 255) / 256)), dim3(256), 0, s, lam, k, w.lbits);
+    int64_t nt = d * T;
+    hipLaunchKernelGGL(k_ivf_counts, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, w.bm, w.lbits, d, kt, T,
+                       W64, w.pre0, w.pre1, w.cnt);
+    return hipGetLastError();
+}
+
+__global__ void k_ivf_seg(const int64_t* __restrict__ off, const int64_t* __restrict__ cnt, int64_t d, int32_t T,
+                          int64_t* __restrict__ seg, int32_t* __restrict__ mid) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t nt = d * T;
+    if (idx < nt) {
+        seg[idx] = off[idx * 2];
+        mid[idx] = (int32_t)cnt[idx * 2];
+    } else if (idx == nt) {
+        seg[nt] = off[nt * 2];
+    }
+}
+
+hipError_t ivf_offsets(int64_t d, int32_t T, IvfBuildWs w, int64_t* seg, int32_t* mid, hipStream_t s) {
+    const int64_t n = d * T * 2;
+    hipError_t e = exclusive_scan_i64(w.cnt, w.off, n, w.scan_ws, s);
+    if (e != hipSuccess) return e;
+    int64_t nt = d * T + 1;
+    hipLaunchKernelGGL(k_ivf_seg, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, w.off, w.cnt, d, T, seg, mid);
+    return hipGetLastError();
+}
+
+__global__ void k_ivf_fill(Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* __restrict__ lam,
+                           const unsigned long long* __restrict__ bm, const unsigned long long* __restrict__ lbits,
+                           const uint16_t* __restrict__ pre0, const uint16_t* __restrict__ pre1,
+                           const int64_t* __restrict__ off, uint16_t* __restrict__ cid, float* __restrict__ v32,
+                           uint16_t* __restrict__ v16, double* __restrict__ v64) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < k; j += nw) {
+        const int part = (lam && lam[j]) ? 1 : 0;
+        const int64_t tile = j / kt, w = j >> 6;
+        const unsigned long long below = (1ull << (j & 63)) - 1ull;
+        const unsigned long long pm = part ? lbits[w] : ~lbits[w];
+        const uint16_t* pre = part ? pre1 : pre0;
+        const uint16_t local = (uint16_t)(j - tile * kt);
+        const int64_t b = st.start[j], m = st.nnz[j];
+        for (int64_t p = lane; p < m; p += 64) {
+            const int64_t t = st.term[b + p];
+            const double u = st.val[b + p];
+            const int64_t rank = pre[w * d + t] + __popcll(bm[w * d + t] & pm & below);
+            const int64_t pos = off[(t * T + tile) * 2 + part] + rank;
+            cid[pos] = local;
+            const float f = (float)u;  // round to nearest even
+            if (v32) v32[pos] = f;
+            if (v16) v16[pos] = f32_to_bf16_rne(f);
+            v64[pos] = u;
+        }
+    }
+}
+
+hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam, IvfBuildWs w,
+                    uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s) {
+    int64_t blocks = ((int64_t)k * 64 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_ivf_fill, dim3((unsigned)blocks), dim3(256), 0, s, st, k, d, kt, T, lam, w.bm, w.lbits,
+                       w.pre0, w.pre1, w.off, cid, v32, v16, v64);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- export to the paper's layout
+__global__ void k_exp_counts(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid, int64_t d, int32_t T,
+                             int64_t* __restrict__ cnt, int32_t* __restrict__ split) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    cnt[t] = seg[(t + 1) * T] - seg[t * T];
+    int64_t sp = 0;
+    for (int32_t tile = 0; tile < T; ++tile) sp += mid[t * T + tile];
+    if (split) split[t] = (int32_t)sp;
+}
+
+__global__ void k_exp_fill(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid,
+                           const uint16_t* __restrict__ cid, const double* __restrict__ v64, int64_t d, int32_t T,
+                           int32_t kt, const int64_t* __restrict__ tptr, int32_t* __restrict__ p_cid,
+                           double* __restrict__ p_val) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t t = wave; t < d; t += nw) {
+        int64_t o = tptr[t];
+        for (int part = 0; part < 2; ++part) {
+            for (int32_t tile = 0; tile < T; ++tile) {
+                int64_t s0 = seg[t * T + tile], s1 = seg[t * T + tile + 1], sm = s0 + mid[t * T + tile];
+                int64_t lo = part ? sm : s0, hi = part ? s1 : sm;
+                for (int64_t p = lo + lane; p < hi; p += 64) {
+                    if (p_cid) p_cid[o + (p - lo)] = (int32_t)cid[p] + tile * kt;
+                    if (p_val) p_val[o + (p - lo)] = v64[p];
+                }
+                o += hi - lo;
+            }
+        }
+    }
+}
+
+hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val,
+                      int64_t* ws_counts, int64_t* scan_ws, hipStream_t s) {
+    const int64_t d = f->d;
+    hipLaunchKernelGGL(k_exp_counts, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, f->seg, f->mid, d, f->T,
+                       ws_counts, split);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (!term_ptr) return hipSuccess;
+    e = exclusive_scan_i64(ws_counts, term_ptr, d, scan_ws, s);
+    if (e != hipSuccess) return e;
+    if (!p_cid && !p_val) return hipSuccess;
+    int64_t blocks = (d * 64 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_exp_fill, dim3((unsigned)blocks), dim3(256), 0, s, f->seg, f->mid, f->cid, f->v64, d, f->T,
+                       f->kt, term_ptr, p_cid, p_val);
+    return hipGetLastError();
+}
+
+}  // namespace sivf

@@ -1,0 +1,118 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, step by
+step (assignments bit-exact, flags and mult-add counts equal, FP64 centroids
+and the structured file bitwise equal)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import device, log, lloyd_parity
+from tests.util import corpus_from_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(**kw):
+    from paper_2103_16141_amd.api import Context
+    return Context(0, **kw)
+
+
+def _X(corpus):
+    from paper_2103_16141_amd.api import DeviceCsr
+    return DeviceCsr.from_corpus(corpus, device())
+
+
+@pytest.mark.parametrize("k_tile,posting", [(0, "fp32"), (64, "fp32"), (64, "bf16")])
+def test_small_f64_trajectory(k_tile, posting):
+    log("small f64 trajectory k_tile=%d posting=%s" % (k_tile, posting))
+    c = synth.make_corpus(3000, 900, 25, 1.0, np.float64, seed=101)
+    ids = synth.init_ids(3000, 150, 7)  # 150 = 64 + 64 + 22: several tiles with a ragged tail
+    ctx = _ctx(k_tile=k_tile, posting_dtype=posting)
+    tr, st = lloyd_parity(ctx, _X(c), c, 150, ids, 12)
+    assert tr.iters >= 5
+
+
+@pytest.mark.parametrize("mode", ["sivf", "ivf", "cbicp"])
+def test_filter_modes_same_assignments(mode):
+    log("filter mode %s" % mode)
+    c = synth.make_corpus(2500, 700, 20, 1.0, np.float64, seed=102)
+    ids = synth.init_ids(2500, 90, 8)
+    ctx = _ctx(k_tile=64, filter_mode=mode)
+    lloyd_parity(ctx, _X(c), c, 90, ids, 15, mode=mode)
+
+
+def test_small_config_f64_k100_ten_iterations():
+    # N=10,000, D=5,000, Poisson(50), Zipf 1.0, f64, k=100, 10 iterations with ICP
+    log("N=10k D=5k k=100 f64")
+    c, ids, w = synth.workload("small-f64")
+    for kt in (0, 64):
+        lloyd_parity(_ctx(k_tile=kt), _X(c), c, w["k"], ids, w["iters"])
+
+
+def test_mid_f32_trajectory():
+    log("N=40k D=20k k=300 f32")
+    c = synth.make_corpus(40000, 20000, 60, 1.1, np.float32, seed=103)
+    ids = synth.init_ids(40000, 300, 9)
+    lloyd_parity(_ctx(k_tile=128), _X(c), c, 300, ids, 8, check_ivf_every=3)
+
+
+def test_bf16_matches_fp32_trajectory_and_counts():
+    log("bf16 vs fp32 counts")
+    c = synth.make_corpus(20000, 8000, 40, 1.1, np.float32, seed=104)
+    ids = synth.init_ids(20000, 200, 10)
+    _, s32 = lloyd_parity(_ctx(posting_dtype="fp32"), _X(c), c, 200, ids, 8, check_ivf_every=4)
+    _, s16 = lloyd_parity(_ctx(posting_dtype="bf16"), _X(c), c, 200, ids, 8, check_ivf_every=4)
+    assert [s["multadds"] for s in s32] == [s["multadds"] for s in s16]
+    assert sum(s["rescored_objects"] for s in s16) >= sum(s["rescored_objects"] for s in s32)
+
+
+# --------------------------------------------------------------------- edge cases
+def test_empty_rows_k1_and_duplicates():
+    log("edge: empty rows, duplicates, k=1")
+    rows = [[0, 3], [], [1, 2, 3], [0, 3], [], [2], [0, 1, 2, 3], [0, 3]]
+    vals = [[0.6, 0.8], [], [0.5, 0.5, 0.7071067811865476], [0.6, 0.8], [], [1.0], [0.5] * 4, [0.6, 0.8]]
+    c = corpus_from_rows(rows, 4, vals)
+    lloyd_parity(_ctx(), _X(c), c, 3, [0, 3, 7], 6)   # three identical seeds: exact ties
+    lloyd_parity(_ctx(), _X(c), c, 1, [2], 4)
+    lloyd_parity(_ctx(), _X(c), c, 8, list(range(8)), 4)
+
+
+def test_single_term_dimension():
+    log("edge: D=1")
+    c = corpus_from_rows([[0]] * 9, 1, 1.0)
+    lloyd_parity(_ctx(), _X(c), c, 4, [3, 1, 5, 0], 4)
+
+
+def test_signed_values_use_the_absolute_bound():
+    log("edge: signed values")
+    c = synth.make_corpus(1500, 300, 15, 1.0, np.float64, seed=105)
+    rng = np.random.default_rng(0)
+    c.val *= np.where(rng.random(c.nnz) < 0.3, -1.0, 1.0)
+    ids = synth.init_ids(1500, 70, 11)
+    lloyd_parity(_ctx(k_tile=64), _X(c), c, 70, ids, 8)
+
+
+def test_long_rows_over_64_terms():
+    log("edge: rows longer than 64 terms")
+    c = synth.make_corpus(2000, 3000, 150, 0.8, np.float32, seed=106)
+    ids = synth.init_ids(2000, 80, 12)
+    lloyd_parity(_ctx(k_tile=64), _X(c), c, 80, ids, 6)
+
+
+def test_run_lloyd_matches_stepwise_and_is_deterministic():
+    log("run_lloyd determinism")
+    c = synth.make_corpus(8000, 3000, 30, 1.1, np.float32, seed=107)
+    ids = synth.init_ids(8000, 120, 13)
+    X = _X(c)
+    ctx = _ctx()
+    a1, own1, ivf1, st1 = ctx.run_lloyd(X, 120, ids, 20)
+    a2, own2, ivf2, st2 = ctx.run_lloyd(X, 120, ids, 20)
+    assert torch.equal(a1, a2) and torch.equal(own1, own2)
+    e1, e2 = ivf1.export(), ivf2.export()
+    for key in e1:
+        assert torch.equal(e1[key], e2[key]), key
+    tr = oracle.lloyd(c, 120, ids, 20, icp=True)
+    assert len(st1) == tr.iters
+    assert np.array_equal(a1.cpu().numpy(), tr.assign[-1])
+    assert [s["multadds"] for s in st1] == tr.multadds

@@ -48,8 +48,8 @@ MUTATIONS = {
         "            for (int64_t p = 0; p < d; ++p) s = s + w[p];",
         [lambda: pins.test_update_matches_dense_numpy(pins.np.float64)]),
     "invariant_part_first": (
-        "            int64_t at = inv ? q1[s]++ : q0[s]++;",
-        "            int64_t at = inv ? q0[s]++ : q1[s]++;",
+        "        q0[s] = term_ptr[s];\n        q1[s] = term_ptr[s] + mf0[s];",
+        "        q0[s] = term_ptr[s] + mf1[s];\n        q1[s] = term_ptr[s];",
         [lambda: pins.test_ivf_layout_and_roundtrip()]),
     "cbicp_counts_invariant": (
         "c += (lam_prev[cid[q]] == 0);",
