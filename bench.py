@@ -1,0 +1,206 @@
+"""Benchmark of the SIVF hot path on one MI355X.
+
+A step is one Lloyd iteration (assignment step + update step, Alg. 1 around
+Alg. 4 / Alg. 5) of the whole path on the headline workload: N = 8,000,000
+L2-normalised sparse rows, D = 140,000 terms, nnz/row ~ Poisson(90), Zipf(1.1)
+term ids, lognormal values (seeded synthetic stand-in for the paper's 8M
+PubMed subset), k = 10,000 seeded initial centroids.  The timed region is
+iterations 1..K of a fresh run from the seeded initial state (W untimed warmup
+iterations are run first on a separate run from the same state).
+
+Reported value: assignment-step object-centroid mult-adds per second with FP32
+postings (sum of posting mult-adds over the timed iterations divided by the
+summed assignment-step time, HIP events on the library's stream), plus s/iter,
+the same for BF16 postings (identical trajectory), the walk kernel's roofline
+figures and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+POSTING_BYTES = {"fp32": 6, "bf16": 4}  # 2-byte centroid id + value
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(stat, nnz, n, n_tiles, posting):
+    """Minimal bytes the walk must move for one launch: every posting once per
+    (object, posting) pair at its minimal encoding, the CSR rows (4-byte column
+    + 4-byte value), two 8-byte segment offsets per (object term, tile), and
+    row pointer / previous assignment / own similarity per object."""
+    return stat["multadds"] * POSTING_BYTES[posting] + nnz * (8 + 16 * n_tiles) + 12 * n
+
+
+def run_lloyd_timed(ctx, X, k, ids, steps, warmup, posting):
+    import torch
+    from paper_2103_16141_amd.api import Lloyd
+
+    if warmup > 0:
+        Lw = Lloyd(ctx, X, k, ids)
+        for _ in range(warmup):
+            Lw.assign()
+            Lw.update()
+        Lw.ivf.free()
+        del Lw
+    torch.cuda.synchronize()
+    L = Lloyd(ctx, X, k, ids)
+    sizes = L.ivf.sizes()
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(1, steps + 1):
+        st = L.assign()
+        up = L.update()
+        st["t_update_ms"] = up["t_update_ms"]
+        stats.append(st)
+        log("%s iter %d: M=%.3e walk %.1f ms assign %.1f ms update %.1f ms moved %d inv %d icp %d rescored %d/%d full %d"
+            % (posting, r, st["multadds"], st["t_walk_ms"], st["t_assign_ms"], st["t_update_ms"], st["moved"],
+               st["n_invariant"], st["icp_objects"], st["rescored_objects"], st["rescored_candidates"],
+               st["full_rescored"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assign_a = L.a.clone()
+    L.ivf.free()
+    return stats, wall, sizes, assign_a
+
+
+def summarize(stats, wall, sizes, nnz, n, posting):
+    M = sum(s["multadds"] for s in stats)
+    t_assign = sum(s["t_assign_ms"] for s in stats) / 1e3
+    t_walk = sum(s["t_walk_ms"] for s in stats) / 1e3
+    t_update = sum(s["t_update_ms"] for s in stats) / 1e3
+    bytes_ = sum(algorithmic_bytes(s, nnz, n, sizes["n_tiles"], posting) for s in stats)
+    return dict(multadds=M, multadds_per_s=M / t_assign, s_per_iter=wall / len(stats),
+                assign_s=t_assign, walk_s=t_walk, update_s=t_update,
+                walk_multadds_per_s=M / t_walk, walk_algorithmic_gbs=bytes_ / t_walk / 1e9,
+                iter1_multadds_per_s=stats[0]["multadds"] / (stats[0]["t_assign_ms"] / 1e3),
+                rescored_objects=sum(s["rescored_objects"] for s in stats),
+                full_rescored=sum(s["full_rescored"] for s in stats),
+                walk_avg_ms=1e3 * t_walk / len(stats))
+
+
+def cpu_baseline(corpus, ids, k, budget_s=15.0):
+    """FP64 oracle assignment (iteration 1, against the seeded initial centroids)
+    on a bounded sample of objects, in posting mult-adds per second."""
+    import numpy as np
+
+    import oracle
+
+    cents = oracle.init_centroids(corpus, ids)
+    _, per_row = oracle.multadds(corpus, oracle.build_ivf(cents, None), per_row=True)
+    rng = np.random.default_rng(0)
+    m, rows_done, total_m, total_t = 256, 0, 0, 0.0
+    while total_t < budget_s:
+        rows = np.sort(rng.choice(corpus.n, m, replace=False))
+        t0 = time.perf_counter()
+        oracle.assign(corpus, cents, rows=rows)
+        dt = time.perf_counter() - t0
+        total_m += int(per_row[rows].sum())
+        total_t += dt
+        rows_done += m
+        if dt < budget_s / 8:
+            m *= 2
+    return dict(value=total_m / total_t, unit="mult-adds/s", cores=oracle.num_threads(), kind="oracle",
+                sample="%d uniformly drawn objects of the same workload at iteration 1 (FP64 inner products "
+                       "against the %d seeded initial centroids), %.1f s of CPU work" % (rows_done, k, total_t))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=None, help="override N (smaller runs for development)")
+    ap.add_argument("--skip-bf16", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--k-tile", type=int, default=0, help="centroids per LDS tile (0 = automatic)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one GPU per run).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2103_16141_amd import _native
+    from paper_2103_16141_amd.api import Context, DeviceCsr
+
+    _native.load()
+    over = {} if args.n is None else {"n": args.n}
+    t0 = time.perf_counter()
+    corpus, ids, w = synth.workload("8m-f32", **over)
+    log("corpus N=%d D=%d nnz=%d generated in %.1f s (%d threads)" % (corpus.n, corpus.d, corpus.nnz,
+                                                                    time.perf_counter() - t0, synth.num_threads()))
+    dev = torch.device("cuda", 0)
+    X = DeviceCsr.from_corpus(corpus, dev)
+    torch.cuda.synchronize()
+    k = w["k"]
+
+    ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile)
+    st32, wall32, sizes, a32 = run_lloyd_timed(ctx32, X, k, ids, args.steps, args.warmup, "fp32")
+    s32 = summarize(st32, wall32, sizes, corpus.nnz, corpus.n, "fp32")
+    ctx32.close()
+    out_bf16 = None
+    if not args.skip_bf16:
+        ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile)
+        st16, wall16, sizes16, a16 = run_lloyd_timed(ctx16, X, k, ids, args.steps, args.warmup, "bf16")
+        s16 = summarize(st16, wall16, sizes16, corpus.nnz, corpus.n, "bf16")
+        ctx16.close()
+        same = bool(torch.equal(a32, a16)) and [s["multadds"] for s in st32] == [s["multadds"] for s in st16]
+        out_bf16 = dict(value=s16["multadds_per_s"], s_per_iter=s16["s_per_iter"], walk_avg_ms=s16["walk_avg_ms"],
+                        rescored_objects=s16["rescored_objects"], full_rescored=s16["full_rescored"],
+                        identical_trajectory=same, vs_fp32=s16["multadds_per_s"] / s32["multadds_per_s"])
+
+    cpu = None
+    if not args.skip_cpu:
+        cpu = cpu_baseline(corpus, ids, k, args.cpu_budget)
+
+    achieved = s32["walk_algorithmic_gbs"]
+    line = {
+        "metric": "assign-step object-centroid mult-adds/s (FP32 postings) + s/iter at N=8M, k=10k; BF16 vs FP32",
+        "value": s32["multadds_per_s"],
+        "unit": "mult-adds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * s32["s_per_iter"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Lloyd iterations 1..K, N=%d, D=%d, nnz/row~Poisson(%d), Zipf(%.1f) terms, "
+                               "lognormal values, L2-normalised rows, k=%d seeded initial objects"
+                               % (corpus.n, corpus.d, w["lam"], w["zipf_s"], k),
+                   "n": corpus.n, "d": corpus.d, "k": k, "nnz": corpus.nnz, "k_tile": sizes["k_tile"],
+                   "n_tiles": sizes["n_tiles"], "filter": "SIVF (ICP via structured file)"},
+        "s_per_iter": s32["s_per_iter"],
+        "iter1_multadds_per_s": s32["iter1_multadds_per_s"],
+        "assign_s": s32["assign_s"], "update_s": s32["update_s"],
+        "multadds_total": s32["multadds"],
+        "bf16": out_bf16,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_walk_fast<false>", "walk_avg_ms": s32["walk_avg_ms"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
