@@ -122,7 +122,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--n", type=int, default=None, help="override N (smaller runs for development)")
     ap.add_argument("--skip-bf16", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")

@@ -705,15 +705,77 @@ sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const in
     return SIVF_OK;
 }
 
-sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr*, const float*, int32_t, float, float*, double*) {
+sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr* X, const float* C, int32_t k, float tau, float* lse_out,
+                                 double* loss_host) {
     if (!ctx) return SIVF_E_INVALID;
-    return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment not built yet");
+    DevGuard g(ctx->device);
+    if (!C || !lse_out) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    if (k < 1) return fail(ctx, SIVF_E_SHAPE, "k must be >= 1");
+    if (!(tau > 0.0f) || !std::isfinite(tau)) return fail(ctx, SIVF_E_INVALID, "tau must be positive and finite");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, false));
+    if (Xc.f64) return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment takes SIVF_F32 object values");
+    float* CT = nullptr;
+    double* loss = nullptr;
+    STCHK(ws(ctx, "soft_CT", (int64_t)k * Xc.d, &CT));
+    STCHK(ws(ctx, "soft_loss", 1, &loss));
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, soft_transpose(C, CT, k, Xc.d, s));
+    HIPCHK(ctx, soft_forward(Xc.n, Xc.rp, Xc.col, (const float*)Xc.val, CT, k, tau, lse_out, loss, ctx->n_cu, s));
+    if (loss_host) {
+        HIPCHK(ctx, hipMemcpyAsync(loss_host, loss, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+    }
+    return SIVF_OK;
 }
 
-sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr*, const float*, int32_t, float, const float*, float,
-                                 float*, float*) {
+sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* C, int32_t k, float tau, const float* lse,
+                                 float grad_loss, float* dC_out, float* dxval_out) {
     if (!ctx) return SIVF_E_INVALID;
-    return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment not built yet");
+    DevGuard g(ctx->device);
+    if (!C || !lse) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    if (k < 1) return fail(ctx, SIVF_E_SHAPE, "k must be >= 1");
+    if (!(tau > 0.0f) || !std::isfinite(tau)) return fail(ctx, SIVF_E_INVALID, "tau must be positive and finite");
+    if (!std::isfinite(grad_loss)) return fail(ctx, SIVF_E_NONFINITE, "grad_loss must be finite");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, false));
+    if (Xc.f64) return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment takes SIVF_F32 object values");
+    if (!dC_out && !dxval_out) return SIVF_OK;
+    const int64_t n = Xc.n, d = Xc.d;
+    hipStream_t s = ctx->stream;
+    float *CT = nullptr, *dS = nullptr, *dxv = dxval_out, *dCT = nullptr;
+    STCHK(ws(ctx, "soft_CT", (int64_t)k * d, &CT));
+    // rows per chunk: dS of one chunk is at most 256 MiB
+    const int64_t rc = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(n, 1), (int64_t)(64ll << 20) / k));
+    STCHK(ws(ctx, "soft_dS", rc * (int64_t)k, &dS));
+    if (!dxv) STCHK(ws(ctx, "soft_dx", std::max<int64_t>(Xc.nnz, 1), &dxv));
+    HIPCHK(ctx, soft_transpose(C, CT, k, d, s));
+    int64_t *cnt = nullptr, *colptr = nullptr, *sws = nullptr;
+    int32_t *hist = nullptr, *xt_row = nullptr;
+    float* xt_val = nullptr;
+    if (dC_out) {
+        const int64_t nb = (n + 1023) / 1024;
+        STCHK(ws(ctx, "soft_dCT", (int64_t)k * d, &dCT));
+        STCHK(ws(ctx, "csc_hist", std::max<int64_t>(nb * d, 1), &hist));
+        STCHK(ws(ctx, "csc_cnt", d, &cnt));
+        STCHK(ws(ctx, "csc_ptr", d + 1, &colptr));
+        STCHK(ws(ctx, "csc_row", std::max<int64_t>(Xc.nnz, 1), &xt_row));
+        STCHK(ws(ctx, "csc_val", std::max<int64_t>(Xc.nnz, 1), &xt_val));
+        STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(d + 1, n + 1)) + 8, &sws));
+        HIPCHK(ctx, soft_csc(n, d, Xc.nnz, Xc.rp, Xc.col, (const float*)Xc.val, hist, cnt, colptr, sws, xt_row, xt_val, s));
+    }
+    int first = 1;
+    for (int64_t c0 = 0; c0 < n || first; c0 += rc) {
+        const int64_t c1 = std::min(n, c0 + rc);
+        if (c1 > c0)
+            HIPCHK(ctx, soft_bwd_rows(c0, c1, Xc.rp, Xc.col, (const float*)Xc.val, CT, k, tau, grad_loss, lse, dS, dxv,
+                                      ctx->n_cu, s));
+        if (dC_out) HIPCHK(ctx, soft_dct(d, k, c0, c1, first, colptr, xt_row, xt_val, dS, dCT, ctx->n_cu, s));
+        first = 0;
+        if (c1 >= n) break;
+    }
+    if (dC_out) HIPCHK(ctx, soft_transpose(dCT, dC_out, d, k, s));
+    return SIVF_OK;
 }
 
 }  // extern "C"

@@ -119,6 +119,7 @@ hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
 // validation: flags[0] |= error bits, flags[1] = min bad row, flags[2] = any negative
 hipError_t validate_csr(const int64_t* rp, const int32_t* col, const void* val, int f64, int64_t n,
@@ -188,5 +189,18 @@ hipError_t upd_bounds(int32_t k, int64_t d, const uint8_t* lam, int allow_copy, 
                       hipStream_t s);
 hipError_t upd_segsum(const Csr& X, int32_t k, const uint8_t* lam, int allow_copy, const Store prev,
                       Store next, UpdateWs w, hipStream_t s);
+
+// soft assignment
+hipError_t soft_transpose(const float* in, float* out, int64_t R, int64_t Cn, hipStream_t s);
+hipError_t soft_forward(int64_t N, const int64_t* rp, const int32_t* col, const float* xv, const float* CT, int32_t k,
+                        float tau, float* lse, double* loss_dev, int n_cu, hipStream_t s);
+hipError_t soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* rp, const int32_t* col, const float* xv,
+                         const float* CT, int32_t k, float tau, float grad, const float* lse, float* dS, float* dxv,
+                         int n_cu, hipStream_t s);
+hipError_t soft_csc(int64_t N, int64_t d, int64_t nnz, const int64_t* rp, const int32_t* col, const float* xv,
+                    int32_t* hist, int64_t* cnt, int64_t* colptr, int64_t* scan_ws, int32_t* xt_row, float* xt_val,
+                    hipStream_t s);
+hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, const int64_t* colptr,
+                    const int32_t* xt_row, const float* xt_val, const float* dS, float* dCT, int n_cu, hipStream_t s);
 
 }  // namespace sivf

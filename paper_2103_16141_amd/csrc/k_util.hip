@@ -27,6 +27,7 @@ hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { return fil
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) { return fill_any(p, v, n, s); }
 hipError_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) { return fill_any(p, v, n, s); }
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s) { return fill_any(p, v, n, s); }
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { return fill_any(p, v, n, s); }
 
 // ---------------------------------------------------------------- scan
 // out[i] = sum_{j < i} in[j] for i in [0, n], three phases: per-chunk totals,

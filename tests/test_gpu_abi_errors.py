@@ -1,0 +1,127 @@
+"""Every status the boundary reports, forced from the host, and outputs left
+untouched on validation errors.  Validation itself runs on the device, so
+these tests need the GPU; no case makes a kernel fault: invalid inputs are
+rejected before any kernel indexes with them."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import log
+from tests.util import corpus_from_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(**kw):
+    from paper_2103_16141_amd.api import Context
+    return Context(0, **kw)
+
+
+def _X(c):
+    from paper_2103_16141_amd.api import DeviceCsr
+    return DeviceCsr.from_corpus(c, torch.device("cuda", 0))
+
+
+def _status(fn):
+    from paper_2103_16141_amd._native import SivfError
+    with pytest.raises(SivfError) as e:
+        fn()
+    return e.value.name
+
+
+def _good():
+    return synth.make_corpus(200, 100, 8, 1.0, np.float32, seed=1)
+
+
+def test_invalid_csr_statuses():
+    log("abi errors: csr")
+    ctx = _ctx()
+    c = _good()
+    bad = _good()
+    bad.col = bad.col.copy()
+    r = int(np.argmax(np.diff(bad.row_ptr) >= 2))
+    a = bad.row_ptr[r]
+    bad.col[a], bad.col[a + 1] = bad.col[a + 1], bad.col[a]       # unsorted row
+    assert _status(lambda: ctx.validate(_X(bad))) == "SIVF_E_UNSORTED"
+    rng = _good()
+    rng.col = rng.col.copy()
+    rng.col[rng.row_ptr[3 + 1] - 1] = rng.d + 5                   # column out of range (last in its row)
+    assert _status(lambda: ctx.validate(_X(rng))) == "SIVF_E_RANGE"
+    nan = _good()
+    nan.val = nan.val.copy()
+    nan.val[17] = np.nan
+    assert _status(lambda: ctx.validate(_X(nan))) == "SIVF_E_NONFINITE"
+    ok = _X(c)
+    ctx.validate(ok)
+    assert _status(lambda: ctx.init_centroids(ok, 0, [])) == "SIVF_E_SHAPE"
+    assert _status(lambda: ctx.init_centroids(ok, 201, list(range(201)))) == "SIVF_E_SHAPE"
+    assert _status(lambda: ctx.init_centroids(ok, 2, [0, 999])) == "SIVF_E_RANGE"
+
+
+def test_outputs_untouched_on_error():
+    log("abi errors: outputs untouched")
+    from paper_2103_16141_amd.api import DeviceCsr
+    ctx = _ctx()
+    c = _good()
+    X = _X(c)
+    ivf = ctx.init_centroids(X, 5, [0, 1, 2, 3, 4])
+    a = torch.full((c.n,), 7, dtype=torch.int32, device="cuda")   # 7 >= k: invalid a^[r-1]
+    own = torch.full((c.n,), 0.25, dtype=torch.float32, device="cuda")
+    lam = torch.full((5,), 9, dtype=torch.uint8, device="cuda")
+    assert _status(lambda: ctx.assign(X, ivf, 2, a, own, lam)) == "SIVF_E_RANGE"
+    assert bool((a == 7).all()) and bool((own == 0.25).all()) and bool((lam == 9).all())
+    assert _status(lambda: ctx.update(X, a, lam, ivf)) == "SIVF_E_RANGE"
+    # column-count mismatch
+    c2 = synth.make_corpus(50, 60, 8, 1.0, np.float32, seed=2)
+    X2 = DeviceCsr.from_corpus(c2, torch.device("cuda", 0))
+    a2 = torch.zeros(c2.n, dtype=torch.int32, device="cuda")
+    own2 = torch.zeros(c2.n, dtype=torch.float32, device="cuda")
+    assert _status(lambda: ctx.assign(X2, ivf, 1, a2, own2, lam)) == "SIVF_E_SHAPE"
+    assert bool((lam == 9).all())
+    # a valid call after the errors still works
+    st = ctx.assign(X, ivf, 1, a, own, lam)
+    assert st["moved"] == c.n and int(a.max()) < 5
+
+
+def test_null_pointers_and_bad_options():
+    from paper_2103_16141_amd import _native as N
+    lib = N.load()
+    h = ctypes.c_void_p()
+    opt = N.sivf_options()
+    lib.sivf_default_options(ctypes.byref(opt))
+    opt.k_tile = 100                                              # not a multiple of 64
+    assert lib.sivf_create(ctypes.byref(h), 0, None, ctypes.byref(opt)) == -1
+    opt.k_tile = 0
+    opt.posting_dtype = N.SIVF_F64                                # postings are f32 or bf16
+    assert lib.sivf_create(ctypes.byref(h), 0, None, ctypes.byref(opt)) == -1
+    assert lib.sivf_create(ctypes.byref(h), 999, None, None) == -7
+    assert lib.sivf_create(None, 0, None, None) == -1
+    ctx = _ctx()
+    assert lib.sivf_validate_csr(ctx.handle, None) == -1
+    assert b"NULL" in lib.sivf_last_error(ctx.handle)
+    st = N.sivf_iter_stats()
+    assert lib.sivf_assign(ctx.handle, None, None, 1, None, None, None, ctypes.byref(st)) == -1
+    assert lib.sivf_destroy(None) == 0 and lib.sivf_ivf_free(ctx.handle, None) == 0
+
+
+def test_workspace_cap_reports_nomem():
+    log("abi errors: workspace cap")
+    ctx = _ctx(workspace_cap_bytes=4096)
+    c = _good()
+    X = _X(c)
+    assert _status(lambda: ctx.init_centroids(X, 5, [0, 1, 2, 3, 4])) == "SIVF_E_NOMEM"
+    ctx2 = _ctx(workspace_cap_bytes=1 << 30)
+    a, own, ivf, stats = ctx2.run_lloyd(X, 5, [0, 1, 2, 3, 4], 5)
+    assert len(stats) >= 1
+
+
+def test_empty_matrix_and_zero_rows():
+    log("abi: empty X")
+    ctx = _ctx()
+    c = corpus_from_rows([[0], [1]], 3, 1.0, dtype=np.float32)
+    X = _X(c)
+    a, own, ivf, stats = ctx.run_lloyd(X, 2, [0, 1], 3)
+    assert a.cpu().tolist() == [0, 1] and stats[-1]["moved"] == 0
