@@ -207,7 +207,9 @@ sivf_status store_reserve(sivf_ctx* ctx, sivf_ivf* f, Store* st, int64_t cap) {
 }
 
 sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
-    if (f->pcap >= P && f->cid) return SIVF_OK;
+    // spare entries: the walk reads postings in aligned groups of 8, which
+    // may reach up to 7 entries past the last one
+    if (f->pcap >= P + 8 && f->cid) return SIVF_OK;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     dev_free(ctx, f->cid, (size_t)f->pcap * 2, &f->bytes);
     dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
@@ -218,7 +220,7 @@ sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
     f->v16 = nullptr;
     f->v64 = nullptr;
     f->pcap = 0;
-    int64_t c = std::max<int64_t>(P + P / 8, 64);
+    int64_t c = std::max<int64_t>(P + P / 8 + 8, 64);
     STCHK(dev_alloc(ctx, (void**)&f->cid, (size_t)c * 2, &f->bytes));
     if (f->pdt == SIVF_BF16) {
         STCHK(dev_alloc(ctx, (void**)&f->v16, (size_t)c * 2, &f->bytes));
@@ -572,7 +574,7 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     HIPCHK(ctx, fill_u8(changed, 0, k, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
     if (n > 0) {
-        const int bpc = walk_blocks_per_cu(f->kt, f->pdt == SIVF_BF16);
+        const int bpc = walk_blocks_per_cu(f->kt, f->pdt == SIVF_BF16, A.cbicp);
         HIPCHK(ctx, walk_fast(A, f->pdt == SIVF_BF16, ctx->n_cu * bpc * kWalkWaves, s));
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));

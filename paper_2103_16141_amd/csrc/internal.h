@@ -14,6 +14,7 @@ namespace sivf {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kCandCap = 32;       // candidate-list capacity per object in the fast pass
+constexpr int kTermCap = 256;      // object terms staged in LDS per wave by the fast pass
 constexpr int kWalkWaves = 4;      // waves per workgroup in the walk kernels
 constexpr int kMaxTile = 4096;     // largest similarity tile (centroids) per wave
 
@@ -158,7 +159,7 @@ hipError_t store_export(const Store st, int32_t k, const int64_t* c_ptr, int32_t
 
 // assignment
 hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, hipStream_t s);
-int walk_blocks_per_cu(int kt, int pdt_bf16);
+int walk_blocks_per_cu(int kt, int pdt_bf16, int cbicp);
 hipError_t rescore_candidates(const WalkArgs& a, const Store st, int64_t grid_waves, hipStream_t s);
 hipError_t rescore_full(const WalkArgs& a, const double* v64, const Store st, int64_t grid, hipStream_t s);
 hipError_t finalize_assign(int64_t n, int iter, const int32_t* a_new, const float* own_new, int32_t* a_io,

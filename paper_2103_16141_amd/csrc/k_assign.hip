@@ -1,11 +1,16 @@
-// Assignment step (Alg. 4) on CDNA: a wave takes one object, loads its CSR
-// row, and for each centroid tile walks the posting lists of the object's
-// terms, gather-accumulating v * u into a per-wave similarity tile in LDS.
-// Centroid ids are unique inside a list, so the 64 lanes of one instruction
-// never collide: the tile is updated with plain LDS read-add-write (a wave's
-// LDS operations complete in order), and the accumulation order is fixed:
-// term-major, ascending term.  (LDS float atomics are ~25x slower on gfx950.)  An object whose own cluster was invariant (ICP branch)
-// stops each list at the moving/invariant boundary of the structured file.
+// Assignment step (Alg. 4) on CDNA: a wave takes one object, stages its
+// terms in LDS, and for each centroid tile walks the posting lists of the
+// object's terms, gather-accumulating v * u into a per-wave similarity tile
+// in LDS.  Centroid ids are unique inside a list, so the lanes of one
+// instruction never collide: the tile is updated with plain LDS
+// read-add-write (a wave's LDS operations complete in order; LDS float
+// atomics are ~25x slower on gfx950), and the accumulation order is fixed:
+// term-major, ascending term.  Postings are fetched 256 at a time through
+// per-list buffer descriptors, with the next batch's loads in flight while
+// the current one is accumulated; this keeps the scalar and vector
+// instruction count per posting low, which is what bounds the walk.  An
+// object whose own cluster was invariant (ICP branch) stops each list at the
+// moving/invariant boundary of the structured file.
 //
 // Exactness: the FP32 pass gives rho_hat with |rho_hat - rho_fp64| <= B per
 // centroid (rounding of posting values, of object values, of the FP32 fold
@@ -73,16 +78,105 @@ __device__ inline float posting_val(const void* pv, int64_t p) {
     return ((const float*)pv)[p];
 }
 
+// Buffer descriptor over `bytes` bytes from `base`: reads past the extent
+// return 0 instead of touching memory.  Word 3 is the gfx9 raw-buffer format
+// (32-bit data format, no swizzle, no stride).
+__device__ inline __amdgpu_buffer_rsrc_t span_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// 256 postings of one list in two halves of 128: lane l holds postings 2l
+// and 2l+1 of each half, fetched as whole words (the compiler then never
+// widens or packs 16-bit values while their loads are in flight).
+//   ca, cb    : two 16-bit ids each (low half = even posting)
+//   ua*, ub*  : binary32 values (fp32), or two bf16 values in ua0 / ub0
+constexpr int kBatch = 256;
+
+struct Batch {
+    uint32_t ca, cb, ua0, ua1, ub0, ub1;
+};
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <bool BF16>
+__device__ inline Batch load_batch(__amdgpu_buffer_rsrc_t dc, __amdgpu_buffer_rsrc_t dv, int off, int lane) {
+    Batch b;
+    b.ca = __builtin_amdgcn_raw_buffer_load_b32(dc, lane * 4, off * 2, 0);
+    b.cb = __builtin_amdgcn_raw_buffer_load_b32(dc, lane * 4 + 256, off * 2, 0);
+    if (BF16) {
+        b.ua0 = __builtin_amdgcn_raw_buffer_load_b32(dv, lane * 4, off * 2, 0);
+        b.ub0 = __builtin_amdgcn_raw_buffer_load_b32(dv, lane * 4 + 256, off * 2, 0);
+        b.ua1 = 0;
+        b.ub1 = 0;
+    } else {
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(dv, lane * 8, off * 4, 0);
+        const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(dv, lane * 8 + 512, off * 4, 0);
+        b.ua0 = a.x;
+        b.ua1 = a.y;
+        b.ub0 = c.x;
+        b.ub1 = c.y;
+    }
+    return b;
+}
+
+// sim[c] += vq * u for the batch's postings whose position relative to the
+// batch start lies in [bs, be).  They belong to one list, so their ids are
+// distinct: all four are read first, then written.  In a partial batch the
+// lanes outside the list use their own spare slot sim[kt + lane] instead
+// (no branches).  CB (IVF-CBICP) zeroes the products of invariant centroids
+// instead of stopping lists early.
+template <bool BF16, bool CB>
+__device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Batch& b, int bs, int be, float vq,
+                                        int lane, bool test_flag, int32_t base) {
+    uint32_t c[4] = {b.ca & 0xffffu, b.ca >> 16, b.cb & 0xffffu, b.cb >> 16};
+    float u[4];
+    if (BF16) {
+        u[0] = __uint_as_float(b.ua0 << 16);
+        u[1] = __uint_as_float(b.ua0 & 0xffff0000u);
+        u[2] = __uint_as_float(b.ub0 << 16);
+        u[3] = __uint_as_float(b.ub0 & 0xffff0000u);
+    } else {
+        u[0] = __uint_as_float(b.ua0);
+        u[1] = __uint_as_float(b.ua1);
+        u[2] = __uint_as_float(b.ub0);
+        u[3] = __uint_as_float(b.ub1);
+    }
+    float pr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pr[i] = vq * u[i];
+    if (!(bs <= 0 && be >= kBatch)) {
+        // position of posting i of this lane: 2 * lane + 128 * (i / 2) + i % 2
+        const uint32_t rel = (uint32_t)(2 * lane - bs), n = (uint32_t)(be - bs);
+        const uint32_t spare = (uint32_t)(A.kt + lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (rel + 128 * (i / 2) + (i % 2) >= n) c[i] = spare;
+    }
+    if (CB && test_flag) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if ((int)c[i] < A.kt && A.lam[base + c[i]]) pr[i] = 0.0f;
+    }
+    const float o0 = sim[c[0]], o1 = sim[c[1]], o2 = sim[c[2]], o3 = sim[c[3]];
+    sim[c[0]] = o0 + pr[0];
+    sim[c[1]] = o1 + pr[1];
+    sim[c[2]] = o2 + pr[2];
+    sim[c[3]] = o3 + pr[3];
+}
+
 // ---------------------------------------------------------------------------
 // fast pass
 // ---------------------------------------------------------------------------
-template <bool BF16>
+template <bool BF16, bool CB>
 __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long long* __restrict__ work) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    float* sim = lds + wid * A.kt;
-    int32_t* cj = (int32_t*)(lds + kWalkWaves * A.kt) + wid * kCandCap;
-    float* cr = (float*)((int32_t*)(lds + kWalkWaves * A.kt) + kWalkWaves * kCandCap) + wid * kCandCap;
+    const int kts = A.kt + 64;   // tile plus one spare slot per lane
+    float* sim = lds + wid * kts;
+    int32_t* cj = (int32_t*)(lds + kWalkWaves * kts) + wid * kCandCap;
+    float* cr = (float*)((int32_t*)(lds + kWalkWaves * kts) + kWalkWaves * kCandCap) + wid * kCandCap;
+    int32_t* tt = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap)) + wid * kTermCap;
+    float* tv = lds + kWalkWaves * (kts + 2 * kCandCap + kTermCap) + wid * kTermCap;
 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
@@ -129,127 +223,178 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 }
                 ccount = 1;
             }
-            const bool front_only = icp && !A.cbicp;
-            const bool test_flag = icp && A.cbicp;
+            const bool front_only = icp && !CB;
+            const bool test_flag = icp && CB;
 
-            for (int tile = 0; tile < A.T; ++tile) {
+            // Stage the object's first kTermCap terms and values in LDS once
+            // (each lane later reads only the entries it wrote itself).
+            for (int h = lane; h < min(n, kTermCap); h += 64) {
+                tt[h] = A.col[r0 + h];
+                tv[h] = load_xval(A.xval, A.x_f64, r0 + h);
+            }
+            // Work is a sequence of (tile, term chunk) pairs, tile-major; an
+            // empty row still has one pair per tile so every tile is closed.
+            const int nch = max(1, (n + 63) >> 6);
+            const int npairs = A.T * nch;
+            int64_t ns0 = 0, ns1 = 0;
+            int32_t nmv = 0;
+            // segment bounds of pair pi, issued one pair ahead of their use
+            auto seg_load = [&](int pi) {
+                const int tl = pi / nch;
+                const int h = (pi - tl * nch) * 64 + lane;
+                ns0 = 0;
+                ns1 = 0;
+                nmv = 0;
+                if (h < n) {
+                    const int64_t t = h < kTermCap ? (int64_t)tt[h] : (int64_t)A.col[r0 + h];
+                    const int64_t sidx = t * A.T + tl;
+                    ns0 = A.seg[sidx];
+                    ns1 = A.seg[sidx + 1];
+                    nmv = A.mid[sidx];
+                }
+            };
+            seg_load(0);
+            for (int pi = 0; pi < npairs; ++pi) {
+                const int tile = pi / nch;
+                const int ch = pi - tile * nch;
                 const int32_t base = tile * A.kt;
                 const int32_t width = min(A.kt, A.k - base);
-                // ---- walk the lists of the object's terms for this tile
-                for (int c0 = 0; c0 < n; c0 += 64) {
-                    const int h = c0 + lane;
-                    int64_t s0 = 0, s1 = 0;
-                    int32_t mv = 0;
-                    float v = 0.0f;
-                    if (h < n) {
-                        const int64_t t = A.col[r0 + h];
-                        v = load_xval(A.xval, A.x_f64, r0 + h);
-                        const int64_t sidx = t * A.T + tile;
-                        s0 = A.seg[sidx];
-                        s1 = A.seg[sidx + 1];
-                        mv = A.mid[sidx];
-                    }
-                    const int64_t e = front_only ? s0 + mv : s1;
-                    const int cnt = min(64, n - c0);
-                    for (int q = 0; q < cnt; ++q) {
-                        const int64_t ps = bcast_i64(s0, q);
-                        const int64_t pe = bcast_i64(e, q);
-                        const float vq = bcast_f32(v, q);
-                        macc += test_flag ? (unsigned long long)bcast_i32(mv, q) : (unsigned long long)(pe - ps);
-                        int64_t p = ps + lane;
-                        // four postings per lane in flight
-                        for (; p + 192 < pe; p += 256) {
-                            const uint16_t c_a = A.cid[p], c_b = A.cid[p + 64], c_c = A.cid[p + 128],
-                                           c_d = A.cid[p + 192];
-                            const float u_a = posting_val<BF16>(A.pval, p), u_b = posting_val<BF16>(A.pval, p + 64),
-                                        u_c = posting_val<BF16>(A.pval, p + 128),
-                                        u_d = posting_val<BF16>(A.pval, p + 192);
-                            // the four postings belong to one list, so their ids are
-                            // distinct: read all four, then write all four
-                            float pa = vq * u_a, pb = vq * u_b, pc = vq * u_c, pd = vq * u_d;
-                            if (test_flag) {
-                                if (A.lam[base + c_a]) pa = 0.0f;
-                                if (A.lam[base + c_b]) pb = 0.0f;
-                                if (A.lam[base + c_c]) pc = 0.0f;
-                                if (A.lam[base + c_d]) pd = 0.0f;
-                            }
-                            const float oa = sim[c_a], ob = sim[c_b], oc = sim[c_c], od = sim[c_d];
-                            sim[c_a] = oa + pa;
-                            sim[c_b] = ob + pb;
-                            sim[c_c] = oc + pc;
-                            sim[c_d] = od + pd;
+                const int64_t s0 = ns0;
+                const int64_t e = front_only ? s0 + nmv : ns1;
+                const int32_t mv = nmv;
+                if (pi + 1 < npairs) seg_load(pi + 1);
+                const int h = ch * 64 + lane;
+                float v = 0.0f;
+                if (h < n) {
+                    v = h < kTermCap ? tv[h] : load_xval(A.xval, A.x_f64, r0 + h);
+                    macc += test_flag ? (unsigned long long)mv : (unsigned long long)(e - s0);
+                }
+                // ---- walk the non-empty lists of this chunk in ascending term
+                // order, kBatch postings per batch (a batch never spans two
+                // lists); the next batch's loads are in flight while the
+                // current one is accumulated.  Postings are read through
+                // buffer descriptors made per list: the lane offset is a
+                // constant, the batch offset is scalar, and lanes past the
+                // list's end read 0 from the hardware range check.
+                unsigned long long live = ballot(h < n && e > s0);
+                if (live) {
+                    // current list seen from a base aligned to 8 postings:
+                    // positions [lo, hi) relative to the base are the list's
+                    int lo = 0, hi = 0, off = 0;
+                    float lv = 0.0f;
+                    __amdgpu_buffer_rsrc_t dc, dv;
+                    auto next_list = [&]() -> bool {
+                        if (!live) return false;
+                        const int q = __builtin_ctzll(live);
+                        live &= live - 1;
+                        const int64_t ls = bcast_i64(s0, q);
+                        const int64_t b0 = ls & ~(int64_t)7;
+                        lo = (int)(ls - b0);
+                        hi = (int)(bcast_i64(e, q) - b0);
+                        lv = bcast_f32(v, q);
+                        off = 0;
+                        // extent rounded up to whole groups of 8 (the arrays keep
+                        // 8 spare entries past the last posting)
+                        const int64_t span = (hi + 7) & ~7;
+                        dc = span_rsrc(A.cid + b0, span * 2);
+                        dv = BF16 ? span_rsrc((const uint16_t*)A.pval + b0, span * 2)
+                                  : span_rsrc((const float*)A.pval + b0, span * 4);
+                        return true;
+                    };
+                    next_list();
+                    Batch X = load_batch<BF16>(dc, dv, off, lane), Y;
+                    int xs = lo - off, xe = hi - off, ys = 0, ye = 0;
+                    float xv = lv, yv = 0.0f;
+                    off += kBatch;
+                    for (;;) {
+                        if (off >= hi && !next_list()) {
+                            accumulate_batch<BF16, CB>(A, sim, X, xs, xe, xv, lane, test_flag, base);
+                            break;
                         }
-                        for (; p < pe; p += 64) {
-                            const uint16_t c = A.cid[p];
-                            const float u = posting_val<BF16>(A.pval, p);
-                            if (!test_flag || !A.lam[base + c]) sim[c] = sim[c] + vq * u;
+                        Y = load_batch<BF16>(dc, dv, off, lane);
+                        ys = lo - off;
+                        ye = hi - off;
+                        yv = lv;
+                        off += kBatch;
+                        accumulate_batch<BF16, CB>(A, sim, X, xs, xe, xv, lane, test_flag, base);
+                        if (off >= hi && !next_list()) {
+                            accumulate_batch<BF16, CB>(A, sim, Y, ys, ye, yv, lane, test_flag, base);
+                            break;
                         }
+                        X = load_batch<BF16>(dc, dv, off, lane);
+                        xs = lo - off;
+                        xe = hi - off;
+                        xv = lv;
+                        off += kBatch;
+                        accumulate_batch<BF16, CB>(A, sim, Y, ys, ye, yv, lane, test_flag, base);
                     }
                 }
-                // ---- tile epilogue: bounds, running theta, candidates; clears the tile
-                double tmax = -INFINITY;
-                int32_t tj = 0x7fffffff;
-                for (int jj = lane; jj < width; jj += 64) {
-                    const int32_t j = base + jj;
-                    const bool elig = !icp || A.lam[j] == 0;
-                    if (elig) {
-                        const double r = (double)sim[jj];
-                        const double lo = r - bound_of(A, bd, r, j);
-                        if (lo > tmax) {
-                            tmax = lo;
-                            tj = j;
-                        }
-                    }
-                }
-                wave_argmax(tmax, tj);
-                if (tmax > best_lo || (tmax == best_lo && tj < best_j)) {
-                    best_lo = tmax;
-                    best_j = tj;
-                }
-                if (tmax > theta) {
-                    theta = tmax;
-                    // drop earlier candidates that can no longer win
-                    bool keep = false;
-                    int32_t kj = 0;
-                    float kr = 0.0f;
-                    if (lane < ccount && lane < kCandCap) {
-                        kj = cj[lane];
-                        kr = cr[lane];
-                        const double r = (double)kr;
-                        keep = r + bound_of(A, bd, r, kj) >= theta;
-                    }
-                    const unsigned long long km = ballot(keep);
-                    if (!overflow) {
-                        const int pos = lanes_below(km);
-                        if (keep) {
-                            cj[pos] = kj;
-                            cr[pos] = kr;
-                        }
-                        ccount = __popcll(km);
-                    }
-                }
-                for (int jj0 = 0; jj0 < width; jj0 += 64) {
-                    const int jj = jj0 + lane;
-                    bool take = false;
-                    float r32 = 0.0f;
-                    if (jj < width) {
+                if (ch == nch - 1) {
+                    // ---- tile epilogue: bounds, running theta, candidates; clears the tile
+                    double tmax = -INFINITY;
+                    int32_t tj = 0x7fffffff;
+                    for (int jj = lane; jj < width; jj += 64) {
                         const int32_t j = base + jj;
-                        r32 = sim[jj];
-                        sim[jj] = 0.0f;
-                        if (!icp || A.lam[j] == 0) {
-                            const double r = (double)r32;
-                            take = r + bound_of(A, bd, r, j) >= theta;
+                        const bool elig = !icp || A.lam[j] == 0;
+                        if (elig) {
+                            const double r = (double)sim[jj];
+                            const double lo = r - bound_of(A, bd, r, j);
+                            if (lo > tmax) {
+                                tmax = lo;
+                                tj = j;
+                            }
                         }
                     }
-                    const unsigned long long tm = ballot(take);
-                    if (tm && !overflow) {
-                        const int pos = ccount + lanes_below(tm);
-                        if (take && pos < kCandCap) {
-                            cj[pos] = base + jj;
-                            cr[pos] = r32;
+                    wave_argmax(tmax, tj);
+                    if (tmax > best_lo || (tmax == best_lo && tj < best_j)) {
+                        best_lo = tmax;
+                        best_j = tj;
+                    }
+                    if (tmax > theta) {
+                        theta = tmax;
+                        // drop earlier candidates that can no longer win
+                        bool keep = false;
+                        int32_t kj = 0;
+                        float kr = 0.0f;
+                        if (lane < ccount && lane < kCandCap) {
+                            kj = cj[lane];
+                            kr = cr[lane];
+                            const double r = (double)kr;
+                            keep = r + bound_of(A, bd, r, kj) >= theta;
                         }
-                        ccount += __popcll(tm);
-                        if (ccount > kCandCap) overflow = true;
+                        const unsigned long long km = ballot(keep);
+                        if (!overflow) {
+                            const int pos = lanes_below(km);
+                            if (keep) {
+                                cj[pos] = kj;
+                                cr[pos] = kr;
+                            }
+                            ccount = __popcll(km);
+                        }
+                    }
+                    for (int jj0 = 0; jj0 < width; jj0 += 64) {
+                        const int jj = jj0 + lane;
+                        bool take = false;
+                        float r32 = 0.0f;
+                        if (jj < width) {
+                            const int32_t j = base + jj;
+                            r32 = sim[jj];
+                            sim[jj] = 0.0f;
+                            if (!icp || A.lam[j] == 0) {
+                                const double r = (double)r32;
+                                take = r + bound_of(A, bd, r, j) >= theta;
+                            }
+                        }
+                        const unsigned long long tm = ballot(take);
+                        if (tm && !overflow) {
+                            const int pos = ccount + lanes_below(tm);
+                            if (take && pos < kCandCap) {
+                                cj[pos] = base + jj;
+                                cr[pos] = r32;
+                            }
+                            ccount += __popcll(tm);
+                            if (ccount > kCandCap) overflow = true;
+                        }
                     }
                 }
             }
@@ -290,38 +435,45 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
             }
         }
     }
+    macc = (unsigned long long)wave_sum_i64((int64_t)macc);
     if (lane == 0) {
         atomicAdd(&A.counters[0], macc);
         atomicAdd(&A.counters[3], icp_cnt);
     }
 }
 
+// per wave: the similarity tile and its 64 spare slots, the candidate list
+// (ids, values) and the staged terms
+static size_t walk_lds_bytes(int kt) {
+    return (size_t)kWalkWaves * ((size_t)kt + 64 + 2 * kCandCap + 2 * kTermCap) * sizeof(float);
+}
+
+// The four instantiations: posting precision x (SIVF | IVF-CBICP filter).
+static const void* walk_kernel(int bf16, int cb) {
+    return bf16 ? (cb ? (const void*)k_walk_fast<true, true> : (const void*)k_walk_fast<true, false>)
+                : (cb ? (const void*)k_walk_fast<false, true> : (const void*)k_walk_fast<false, false>);
+}
+
 hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, hipStream_t s) {
     // the work counter lives right after the 8 counters
     unsigned long long* work = a.counters + 8;
-    const size_t lds = (size_t)kWalkWaves * a.kt * sizeof(float) + (size_t)kWalkWaves * kCandCap * 8;
+    const size_t lds = walk_lds_bytes(a.kt);
     int blocks = (grid_waves + kWalkWaves - 1) / kWalkWaves;
     if (blocks < 1) blocks = 1;
+    const void* fn = walk_kernel(pdt_bf16, a.cbicp);
     if (lds > 65536) {
-        hipError_t e = pdt_bf16 ? hipFuncSetAttribute((const void*)k_walk_fast<true>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                                : hipFuncSetAttribute((const void*)k_walk_fast<false>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (pdt_bf16)
-        hipLaunchKernelGGL(k_walk_fast<true>, dim3(blocks), dim3(64 * kWalkWaves), lds, s, a, work);
-    else
-        hipLaunchKernelGGL(k_walk_fast<false>, dim3(blocks), dim3(64 * kWalkWaves), lds, s, a, work);
-    return hipGetLastError();
+    WalkArgs args = a;
+    void* params[] = {&args, &work};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(64 * kWalkWaves), params, lds, s);
 }
 
-int walk_blocks_per_cu(int kt, int pdt_bf16) {
-    const size_t lds = (size_t)kWalkWaves * kt * sizeof(float) + (size_t)kWalkWaves * kCandCap * 8;
+int walk_blocks_per_cu(int kt, int pdt_bf16, int cbicp) {
+    const size_t lds = walk_lds_bytes(kt);
     int nb = 0;
-    hipError_t e = pdt_bf16
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_fast<true>, 64 * kWalkWaves, lds)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_fast<false>, 64 * kWalkWaves, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel(pdt_bf16, cbicp), 64 * kWalkWaves, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
