@@ -66,10 +66,11 @@ def run_lloyd_timed(ctx, X, k, ids, steps, warmup, posting):
         up = L.update()
         st["t_update_ms"] = up["t_update_ms"]
         stats.append(st)
-        log("%s iter %d: M=%.3e walk %.1f ms assign %.1f ms update %.1f ms moved %d inv %d icp %d rescored %d/%d full %d"
+        log("%s iter %d: M=%.3e walk %.1f ms assign %.1f ms update %.1f ms moved %d inv %d icp %d rescored %d/%d "
+            "full %d head rows %d"
             % (posting, r, st["multadds"], st["t_walk_ms"], st["t_assign_ms"], st["t_update_ms"], st["moved"],
                st["n_invariant"], st["icp_objects"], st["rescored_objects"], st["rescored_candidates"],
-               st["full_rescored"]))
+               st["full_rescored"], st["head_rows"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assign_a = L.a.clone()
@@ -128,6 +129,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--k-tile", type=int, default=0, help="centroids per LDS tile (0 = automatic)")
+    ap.add_argument("--head-density", type=float, default=None,
+                    help="dense head rows for terms held by at least this fraction of centroids (default: library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one GPU per run).", file=sys.stderr)
@@ -151,13 +154,13 @@ def main():
     torch.cuda.synchronize()
     k = w["k"]
 
-    ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile)
+    ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile, head_density=args.head_density)
     st32, wall32, sizes, a32 = run_lloyd_timed(ctx32, X, k, ids, args.steps, args.warmup, "fp32")
     s32 = summarize(st32, wall32, sizes, corpus.nnz, corpus.n, "fp32")
     ctx32.close()
     out_bf16 = None
     if not args.skip_bf16:
-        ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile)
+        ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile, head_density=args.head_density)
         st16, wall16, sizes16, a16 = run_lloyd_timed(ctx16, X, k, ids, args.steps, args.warmup, "bf16")
         s16 = summarize(st16, wall16, sizes16, corpus.nnz, corpus.n, "bf16")
         ctx16.close()

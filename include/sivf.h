@@ -89,13 +89,21 @@ typedef struct {
 typedef struct {
     sivf_dtype posting_dtype;   /* SIVF_F32 (default) or SIVF_BF16 posting values */
     int32_t filter_mode;        /* sivf_filter_mode, default SIVF_MODE_SIVF */
-    int32_t k_tile;             /* centroids per LDS similarity tile; 0 = automatic;
+    int32_t k_tile;             /* centroids per LDS similarity tile; 0 = automatic
+                                   (k split evenly into tiles of at most 2048 for
+                                   F32 postings, 1024 for BF16, rounded up to 64);
                                    otherwise a multiple of 64 in [64, 4096] */
     int32_t certify;            /* 1 (default): exact assignments (certificate + FP64
                                    re-score).  0: take the fast-pass argmax as is
                                    (diagnostics only; not exact) */
     size_t workspace_cap_bytes; /* 0 = unlimited; else device bytes the ctx and its
                                    files may hold; exceeding it gives SIVF_E_NOMEM */
+    float head_density;         /* in [0, 1]; default 0.5.  Terms held by at least this
+                                   fraction of the k centroids also get a dense row of
+                                   posting values (zeros for absent centroids) that the
+                                   walk reads for objects outside the ICP branch; 0
+                                   disables.  Same results and mult-add counts either
+                                   way (a memory layout choice, not the paper's). */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */
@@ -113,6 +121,7 @@ typedef struct {
     float t_walk_ms;             /* fast-pass kernel time (HIP events) */
     float t_assign_ms;           /* whole assignment step (walk + re-score + flags) */
     float t_update_ms;           /* whole update step (means + structured file) */
+    int64_t head_rows;           /* dense head rows the walk read (see head_density) */
 } sivf_iter_stats;
 
 typedef struct sivf_ctx sivf_ctx;  /* device, stream, options, workspace, last error */

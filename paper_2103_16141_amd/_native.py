@@ -22,7 +22,8 @@ class sivf_csr(ctypes.Structure):
 
 class sivf_options(ctypes.Structure):
     _fields_ = [("posting_dtype", ctypes.c_int), ("filter_mode", ctypes.c_int32), ("k_tile", ctypes.c_int32),
-                ("certify", ctypes.c_int32), ("workspace_cap_bytes", ctypes.c_size_t)]
+                ("certify", ctypes.c_int32), ("workspace_cap_bytes", ctypes.c_size_t),
+                ("head_density", ctypes.c_float)]
 
 
 class sivf_iter_stats(ctypes.Structure):
@@ -30,7 +31,7 @@ class sivf_iter_stats(ctypes.Structure):
                 ("moved", ctypes.c_int64), ("icp_objects", ctypes.c_int64), ("rescored_objects", ctypes.c_int64),
                 ("rescored_candidates", ctypes.c_int64), ("full_rescored", ctypes.c_int64),
                 ("objective_fast", ctypes.c_double), ("t_walk_ms", ctypes.c_float),
-                ("t_assign_ms", ctypes.c_float), ("t_update_ms", ctypes.c_float)]
+                ("t_assign_ms", ctypes.c_float), ("t_update_ms", ctypes.c_float), ("head_rows", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

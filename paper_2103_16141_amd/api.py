@@ -110,7 +110,7 @@ class Ivf:
 
 class Context:
     def __init__(self, device=0, posting_dtype="fp32", filter_mode="sivf", k_tile=0, certify=True,
-                 workspace_cap_bytes=0, stream=None):
+                 workspace_cap_bytes=0, stream=None, head_density=None):
         lib = N.load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         idx = self.device.index if self.device.index is not None else 0
@@ -121,6 +121,8 @@ class Context:
         opt.k_tile = int(k_tile)
         opt.certify = 1 if certify else 0
         opt.workspace_cap_bytes = int(workspace_cap_bytes)
+        if head_density is not None:
+            opt.head_density = float(head_density)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

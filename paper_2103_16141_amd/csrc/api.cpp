@@ -181,7 +181,8 @@ sivf_status check_assign(sivf_ctx* ctx, const int32_t* a, int64_t n, int32_t k, 
 void choose_tiles(const sivf_ctx* ctx, int32_t k, int32_t* kt, int32_t* T) {
     int32_t want = ctx->opt.k_tile;
     if (want <= 0) {
-        const int32_t kmax = 2048;
+        // widest tile per posting dtype measured fastest at N = 8M, k = 10k
+        const int32_t kmax = ctx->opt.posting_dtype == SIVF_BF16 ? 1024 : 2048;
         int32_t t = (k + kmax - 1) / kmax;
         int32_t w = (k + t - 1) / t;
         want = ((w + 63) / 64) * 64;
@@ -250,6 +251,8 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     dev_free(ctx, f->v64, (size_t)f->pcap * 8, &f->bytes);
     dev_free(ctx, f->lam, (size_t)f->k, &f->bytes);
     dev_free(ctx, f->cnorm, (size_t)f->k * 8, &f->bytes);
+    dev_free(ctx, f->head, (size_t)f->d * 4, &f->bytes);
+    dev_free(ctx, f->hval, (size_t)f->hcap * f->T * f->kt * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
     delete f;
 }
 
@@ -269,6 +272,7 @@ sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mid, (size_t)(d * f->T) * 4, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->lam, (size_t)k, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->cnorm, (size_t)k * 8, &f->bytes);
+    if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->head, (size_t)d * 4, &f->bytes);
     if (st != SIVF_OK) {
         free_file(ctx, f);
         return st;
@@ -292,6 +296,19 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
              &w.scan_ws));
     HIPCHK(ctx, ivf_count(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, ctx->stream));
     HIPCHK(ctx, ivf_offsets(f->d, f->T, w, f->seg, f->mid, ctx->stream));
+    // dense head rows: terms whose lists hold >= ceil(head_density * k) postings
+    int64_t* hflag = nullptr;
+    int64_t* hscan = nullptr;
+    int64_t H = 0;
+    if (f->head) {
+        const int64_t min_len = std::max<int64_t>(1, (int64_t)std::ceil((double)ctx->opt.head_density * f->k));
+        STCHK(ws(ctx, "head_flag", f->d + 1, &hflag));
+        STCHK(ws(ctx, "head_scan", f->d + 1, &hscan));
+        HIPCHK(ctx, head_flags(f->seg, f->d, f->T, min_len, hflag, ctx->stream));
+        HIPCHK(ctx, exclusive_scan_i64(hflag, hscan, f->d, w.scan_ws, ctx->stream));
+        HIPCHK(ctx, head_index(hflag, hscan, f->d, f->head, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(&H, hscan + f->d, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    }
     int64_t P = 0, total = 0;
     int64_t* cscan = nullptr;
     STCHK(ws(ctx, "ivf_cscan", (int64_t)f->k + 1, &cscan));
@@ -304,6 +321,24 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
     STCHK(postings_reserve(ctx, f, P));
     f->P = P;
     HIPCHK(ctx, ivf_fill(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, f->cid, f->v32, f->v16, f->v64, ctx->stream));
+    f->H = 0;
+    if (f->head) {
+        const int64_t kpad = (int64_t)f->T * f->kt, esz = f->pdt == SIVF_BF16 ? 2 : 4;
+        // rows beyond the cap are not built: the walk then reads every list
+        if (H > 0 && H * kpad * esz <= kHeadCapBytes) {
+            if (H > f->hcap) {
+                HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+                dev_free(ctx, f->hval, (size_t)(f->hcap * kpad * esz), &f->bytes);
+                f->hval = nullptr;
+                f->hcap = 0;
+                const int64_t c = std::min<int64_t>(H + H / 8 + 16, kHeadCapBytes / (kpad * esz));
+                STCHK(dev_alloc(ctx, &f->hval, (size_t)(c * kpad * esz), &f->bytes));
+                f->hcap = c;
+            }
+            HIPCHK(ctx, head_fill(f->cur, f->k, f->head, kpad, H, f->pdt == SIVF_BF16, f->hval, ctx->stream));
+            f->H = H;
+        }
+    }
     if (!f->nonneg) HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
     return SIVF_OK;
 }
@@ -320,6 +355,7 @@ sivf_status sivf_default_options(sivf_options* opt) {
     opt->k_tile = 0;
     opt->certify = 1;
     opt->workspace_cap_bytes = 0;
+    opt->head_density = 0.5f;
     return SIVF_OK;
 }
 
@@ -332,6 +368,7 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     if (o.posting_dtype != SIVF_F32 && o.posting_dtype != SIVF_BF16) return SIVF_E_INVALID;
     if (o.filter_mode < 0 || o.filter_mode > 2) return SIVF_E_INVALID;
     if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
+    if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
     sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
@@ -568,6 +605,10 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.fobj = fobj;
     A.counters = counters;
     A.qcap = qcap;
+    A.head = f->H > 0 ? f->head : nullptr;
+    A.hval = f->hval;
+    A.kpad = (int64_t)f->T * f->kt;
+    A.hbytes = f->H * A.kpad * (f->pdt == SIVF_BF16 ? 2 : 4);
 
     hipStream_t s = ctx->stream;
     HIPCHK(ctx, fill_u64(counters, 0ull, 16, s));
@@ -602,6 +643,7 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
         stats_host->moved = (int64_t)c[5];
         stats_host->n_invariant = (int32_t)c[6];
         stats_host->objective_fast = o;
+        stats_host->head_rows = f->H;
         float t = 0.0f;
         HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
         stats_host->t_walk_ms = t;

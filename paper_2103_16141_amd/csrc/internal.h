@@ -15,6 +15,7 @@ namespace sivf {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kCandCap = 32;       // candidate-list capacity per object in the fast pass
 constexpr int kTermCap = 256;      // object terms staged in LDS per wave by the fast pass
+constexpr int64_t kHeadCapBytes = 0xF0000000LL;   // dense head rows beyond this are not built
 constexpr int kWalkWaves = 4;      // waves per workgroup in the walk kernels
 constexpr int kMaxTile = 4096;     // largest similarity tile (centroids) per wave
 
@@ -70,6 +71,11 @@ struct WalkArgs {
     unsigned long long* counters;  // [0] multadds [1] queue len [2] full len [3] icp objects
                                    // [4] re-scored candidates [5] moved [6] invariant [8] work
     int64_t qcap;           // capacity of the candidate queue
+    // dense head rows (nullptr head: none)
+    const int32_t* head;    // [d] row of each term, -1 if none
+    const void* hval;       // [H * kpad] values in the posting dtype
+    int64_t kpad;           // row length: T * kt
+    int64_t hbytes;         // bytes of hval (< 2^32)
 };
 
 }  // namespace sivf
@@ -87,6 +93,9 @@ struct sivf_ivf {
     uint16_t* v16 = nullptr;        // [pcap] (posting dtype bf16)
     double* v64 = nullptr;          // [pcap] FP64 values (exact re-score over whole lists)
     int64_t P = 0, pcap = 0;
+    int32_t* head = nullptr;        // [d] dense head row of each term, -1 if none
+    void* hval = nullptr;           // [hcap * kpad] dense head rows, posting dtype
+    int64_t H = 0, hcap = 0;        // head rows in use / allocated
     uint8_t* lam = nullptr;         // [k]
     double* cnorm = nullptr;        // [k]
     int nonneg = 1;
@@ -152,6 +161,11 @@ hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T
 hipError_t ivf_offsets(int64_t d, int32_t T, IvfBuildWs w, int64_t* seg, int32_t* mid, hipStream_t s);
 hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam,
                     IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s);
+// dense head rows: flag[t] = 1 if term t's lists hold >= min_len postings
+hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s);
+hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s);
+hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int64_t H, int pdt_bf16,
+                     void* hval, hipStream_t s);
 hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val,
                       int64_t* ws_counts, int64_t* scan_ws, hipStream_t s);
 hipError_t store_export(const Store st, int32_t k, const int64_t* c_ptr, int32_t* c_col, double* c_val,

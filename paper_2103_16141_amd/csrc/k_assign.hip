@@ -164,6 +164,70 @@ __device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Bat
     sim[c[3]] = o3 + pr[3];
 }
 
+// Dense head rows: 512 consecutive centroids of one row per batch, lane l
+// holding centroids 4l .. 4l+3 and 256 + 4l .. 256 + 4l+3 (two 16-byte loads
+// for binary32, two 8-byte loads for bf16), so each lane's LDS update is two
+// aligned 16-byte read-add-writes, conflict-free across the wave.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct DBatch {
+    u32x4 a, b;
+};
+
+template <bool BF16>
+__device__ inline DBatch dense_load(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
+    DBatch r;
+    if (BF16) {
+        const int so = (int)(uint32_t)(at * 2);
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(dd, lane * 8, so, 0);
+        const u32x2 y = __builtin_amdgcn_raw_buffer_load_b64(dd, lane * 8 + 512, so, 0);
+        r.a = u32x4{x.x, x.y, 0u, 0u};
+        r.b = u32x4{y.x, y.y, 0u, 0u};
+    } else {
+        const int so = (int)(uint32_t)(at * 4);
+        r.a = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, so, 0);
+        r.b = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16 + 1024, so, 0);
+    }
+    return r;
+}
+
+template <bool BF16>
+__device__ inline void dense_unit(float* sim, u32x4 w, int c0, float xv) {
+    float u0, u1, u2, u3;
+    if (BF16) {
+        u0 = __uint_as_float(w.x << 16);
+        u1 = __uint_as_float(w.x & 0xffff0000u);
+        u2 = __uint_as_float(w.y << 16);
+        u3 = __uint_as_float(w.y & 0xffff0000u);
+    } else {
+        u0 = __uint_as_float(w.x);
+        u1 = __uint_as_float(w.y);
+        u2 = __uint_as_float(w.z);
+        u3 = __uint_as_float(w.w);
+    }
+    float4* q = (float4*)(sim + c0);
+    float4 o = *q;
+    o.x = o.x + xv * u0;
+    o.y = o.y + xv * u1;
+    o.z = o.z + xv * u2;
+    o.w = o.w + xv * u3;
+    *q = o;
+}
+
+// sim[ub + c] += xv * row[ub + c] for the batch's centroids below kt
+template <bool BF16>
+__device__ inline void dense_accumulate(float* sim, const DBatch& b, int ub, int kt, float xv, int lane) {
+    const int c0 = ub + 4 * lane, c1 = ub + 256 + 4 * lane;
+    if (ub + 512 <= kt) {
+        dense_unit<BF16>(sim, b.a, c0, xv);
+        dense_unit<BF16>(sim, b.b, c1, xv);
+    } else {
+        // tile width not a multiple of 512: the lanes past it hold other centroids
+        if (c0 < kt) dense_unit<BF16>(sim, b.a, c0, xv);
+        if (c1 < kt) dense_unit<BF16>(sim, b.b, c1, xv);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // fast pass
 // ---------------------------------------------------------------------------
@@ -177,6 +241,8 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
     float* cr = (float*)((int32_t*)(lds + kWalkWaves * kts) + kWalkWaves * kCandCap) + wid * kCandCap;
     int32_t* tt = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap)) + wid * kTermCap;
     float* tv = lds + kWalkWaves * (kts + 2 * kCandCap + kTermCap) + wid * kTermCap;
+    int32_t* th = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap + 2 * kTermCap)) + wid * kTermCap;
+    const __amdgpu_buffer_rsrc_t dd = span_rsrc(A.hval, A.hbytes);
 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
@@ -229,8 +295,10 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
             // Stage the object's first kTermCap terms and values in LDS once
             // (each lane later reads only the entries it wrote itself).
             for (int h = lane; h < min(n, kTermCap); h += 64) {
-                tt[h] = A.col[r0 + h];
+                const int32_t t = A.col[r0 + h];
+                tt[h] = t;
                 tv[h] = load_xval(A.xval, A.x_f64, r0 + h);
+                th[h] = A.head ? A.head[t] : -1;
             }
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
@@ -276,7 +344,53 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 // buffer descriptors made per list: the lane offset is a
                 // constant, the batch offset is scalar, and lanes past the
                 // list's end read 0 from the hardware range check.
-                unsigned long long live = ballot(h < n && e > s0);
+                // ---- head terms (outside the ICP branch): dense rows, in
+                // ascending term order, 512 centroids per batch, next batch in
+                // flight while the current one is accumulated
+                int hrow = -1;
+                if (A.head && !icp && h < n) hrow = h < kTermCap ? th[h] : A.head[A.col[r0 + h]];
+                unsigned long long dl = ballot(hrow >= 0);
+                if (dl) {
+                    int q = __builtin_ctzll(dl);
+                    dl &= dl - 1;
+                    int ub = 0;
+                    float xv = bcast_f32(v, q);
+                    int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + base;
+                    auto dadv = [&]() -> bool {
+                        ub += 512;
+                        if (ub < A.kt) return true;
+                        if (!dl) return false;
+                        q = __builtin_ctzll(dl);
+                        dl &= dl - 1;
+                        ub = 0;
+                        xv = bcast_f32(v, q);
+                        rb = (int64_t)bcast_i32(hrow, q) * A.kpad + base;
+                        return true;
+                    };
+                    DBatch X = dense_load<BF16>(dd, rb + ub, lane), Y;
+                    int xu = ub, yu = 0;
+                    float xx = xv, yx = 0.0f;
+                    for (;;) {
+                        if (!dadv()) {
+                            dense_accumulate<BF16>(sim, X, xu, A.kt, xx, lane);
+                            break;
+                        }
+                        Y = dense_load<BF16>(dd, rb + ub, lane);
+                        yu = ub;
+                        yx = xv;
+                        dense_accumulate<BF16>(sim, X, xu, A.kt, xx, lane);
+                        if (!dadv()) {
+                            dense_accumulate<BF16>(sim, Y, yu, A.kt, yx, lane);
+                            break;
+                        }
+                        X = dense_load<BF16>(dd, rb + ub, lane);
+                        xu = ub;
+                        xx = xv;
+                        dense_accumulate<BF16>(sim, Y, yu, A.kt, yx, lane);
+                    }
+                }
+                // ---- other terms: structured lists
+                unsigned long long live = ballot(h < n && e > s0 && hrow < 0);
                 if (live) {
                     // current list seen from a base aligned to 8 postings:
                     // positions [lo, hi) relative to the base are the list's
@@ -443,9 +557,9 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
 }
 
 // per wave: the similarity tile and its 64 spare slots, the candidate list
-// (ids, values) and the staged terms
+// (ids, values) and the staged terms (id, value, head row)
 static size_t walk_lds_bytes(int kt) {
-    return (size_t)kWalkWaves * ((size_t)kt + 64 + 2 * kCandCap + 2 * kTermCap) * sizeof(float);
+    return (size_t)kWalkWaves * ((size_t)kt + 64 + 2 * kCandCap + 3 * kTermCap) * sizeof(float);
 }
 
 // The four instantiations: posting precision x (SIVF | IVF-CBICP filter).

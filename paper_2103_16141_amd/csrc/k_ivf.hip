@@ -148,6 +148,77 @@ hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- dense head rows
+// A memory layout of this implementation (not the paper's): a term whose
+// lists hold at least min_len postings gets a row of kpad = T * kt values,
+// one per centroid id (zero where the centroid lacks the term), rounded to
+// the posting dtype exactly as its postings are.  Rows are numbered in term
+// order.
+__global__ void k_head_flags(const int64_t* __restrict__ seg, int64_t d, int32_t T, int64_t min_len,
+                             int64_t* __restrict__ flag) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    flag[t] = (seg[(t + 1) * T] - seg[t * T] >= min_len) ? 1 : 0;
+}
+
+__global__ void k_head_index(const int64_t* __restrict__ flag, const int64_t* __restrict__ scan, int64_t d,
+                             int32_t* __restrict__ head) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    head[t] = flag[t] ? (int32_t)scan[t] : -1;
+}
+
+__global__ void k_head_zero(uint32_t* __restrict__ w, int64_t nw) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nw; i += stride) w[i] = 0u;
+}
+
+// one wave per centroid: scatter its head-term values into the rows
+__global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ head, int64_t kpad,
+                               float* __restrict__ h32, uint16_t* __restrict__ h16) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < k; j += nw) {
+        const int64_t b = st.start[j], m = st.nnz[j];
+        for (int64_t p = lane; p < m; p += 64) {
+            const int32_t r = head[st.term[b + p]];
+            if (r >= 0) {
+                const float f = (float)st.val[b + p];  // round to nearest even
+                if (h32) h32[r * kpad + j] = f;
+                else h16[r * kpad + j] = f32_to_bf16_rne(f);
+            }
+        }
+    }
+}
+
+hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_head_flags, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, seg, d, T, min_len, flag);
+    return hipGetLastError();
+}
+
+hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s) {
+    hipLaunchKernelGGL(k_head_index, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, flag, scan, d, head);
+    return hipGetLastError();
+}
+
+hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int64_t H, int pdt_bf16,
+                     void* hval, hipStream_t s) {
+    const int64_t bytes = H * kpad * (pdt_bf16 ? 2 : 4);
+    const int64_t nw = (bytes + 3) / 4;
+    if (nw == 0) return hipSuccess;
+    int64_t zb = (nw + 255) / 256;
+    if (zb > 65536) zb = 65536;
+    hipLaunchKernelGGL(k_head_zero, dim3((unsigned)zb), dim3(256), 0, s, (uint32_t*)hval, nw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t blocks = ((int64_t)k * 64 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_head_scatter, dim3((unsigned)blocks), dim3(256), 0, s, st, k, head, kpad,
+                       pdt_bf16 ? nullptr : (float*)hval, pdt_bf16 ? (uint16_t*)hval : nullptr);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- export to the paper's layout
 __global__ void k_exp_counts(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid, int64_t d, int32_t T,
                              int64_t* __restrict__ cnt, int32_t* __restrict__ split) {

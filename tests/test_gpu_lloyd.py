@@ -116,3 +116,25 @@ def test_run_lloyd_matches_stepwise_and_is_deterministic():
     assert len(st1) == tr.iters
     assert np.array_equal(a1.cpu().numpy(), tr.assign[-1])
     assert [s["multadds"] for s in st1] == tr.multadds
+
+
+@pytest.mark.parametrize("posting", ["fp32", "bf16"])
+@pytest.mark.parametrize("k,k_tile", [(200, 0), (600, 512)])
+def test_dense_head_rows_same_trajectory(posting, k, k_tile):
+    # Dense head rows for terms held by >= 10% or by all centroids, or none at
+    # all: every variant matches the oracle step by step (assignments, flags,
+    # mult-add counts, centroids), and the rows are really read when enabled.
+    # k_tile 512 runs whole 512-centroid batches; the automatic tile (256 for
+    # k = 200) runs the masked tail of a batch.
+    log("dense head rows posting=%s k=%d k_tile=%d" % (posting, k, k_tile))
+    c = synth.make_corpus(20000, 3000, 40, 1.1, np.float32, seed=104)
+    ids = synth.init_ids(20000, k, 10)
+    rows = {}
+    for hd in (0.0, 0.1, 1.0):
+        ctx = _ctx(k_tile=k_tile, posting_dtype=posting, head_density=hd)
+        tr, st = lloyd_parity(ctx, _X(c), c, k, ids, 6)
+        rows[hd] = [s["head_rows"] for s in st]
+        ctx.close()
+    assert all(r == 0 for r in rows[0.0])
+    assert max(rows[0.1]) > 0
+    assert all(a >= b for a, b in zip(rows[0.1], rows[1.0]))
