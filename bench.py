@@ -30,6 +30,49 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 POSTING_BYTES = {"fp32": 6, "bf16": 4}  # 2-byte centroid id + value
+WALK_KERNEL = "k_walk_fast<false, false>"   # FP32 postings, SIVF filter
+# counter-based HBM traffic of the walk, written from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs; used only while the kernel sources still hash the same
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_8m_k10k_hbm_traffic.md")
+WALK_SOURCES = ["paper_2103_16141_amd/csrc/k_assign.hip", "paper_2103_16141_amd/csrc/internal.h",
+                "paper_2103_16141_amd/csrc/wave.h"]
+
+
+def walk_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed counter profile, or None
+    when the profile is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if line.startswith("TRAFFIC_JSON "):
+                    rec = json.loads(line[len("TRAFFIC_JSON "):])
+                    if rec.get("walk_source_hash") == walk_source_hash():
+                        return rec["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def copy_calibration(gib=1):
+    """A plain device-to-device copy of a known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters (one kernel launch per copy)."""
+    import torch
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
 
 
 def log(msg):
@@ -131,7 +174,16 @@ def main():
     ap.add_argument("--k-tile", type=int, default=0, help="centroids per LDS tile (0 = automatic)")
     ap.add_argument("--head-density", type=float, default=None,
                     help="dense head rows for terms held by at least this fraction of centroids (default: library's)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 3 copies of 1 GiB (counter calibration for the traffic figure)")
+    ap.add_argument("--print-walk-hash", action="store_true", help="print the walk kernel source hash and exit")
     args = ap.parse_args()
+    if args.print_walk_hash:
+        print(walk_source_hash())
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one GPU per run).", file=sys.stderr)
         sys.exit(2)
@@ -198,8 +250,8 @@ def main():
         "multadds_total": s32["multadds"],
         "bf16": out_bf16,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_walk_fast<false>", "walk_avg_ms": s32["walk_avg_ms"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": WALK_KERNEL, "walk_avg_ms": s32["walk_avg_ms"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
