@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--k-tile", type=int, default=0, help="centroids per LDS tile (0 = automatic)")
     ap.add_argument("--head-density", type=float, default=None,
                     help="dense head rows for terms held by at least this fraction of centroids (default: library's)")
+    ap.add_argument("--tiles-per-launch", type=int, default=None,
+                    help="centroid tiles per walk launch (default: library's, one tile per launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 copies of 1 GiB (counter calibration for the traffic figure)")
     ap.add_argument("--print-walk-hash", action="store_true", help="print the walk kernel source hash and exit")
@@ -206,13 +208,15 @@ def main():
     torch.cuda.synchronize()
     k = w["k"]
 
-    ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile, head_density=args.head_density)
+    ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile, head_density=args.head_density,
+                    tiles_per_launch=args.tiles_per_launch)
     st32, wall32, sizes, a32 = run_lloyd_timed(ctx32, X, k, ids, args.steps, args.warmup, "fp32")
     s32 = summarize(st32, wall32, sizes, corpus.nnz, corpus.n, "fp32")
     ctx32.close()
     out_bf16 = None
     if not args.skip_bf16:
-        ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile, head_density=args.head_density)
+        ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile, head_density=args.head_density,
+                    tiles_per_launch=args.tiles_per_launch)
         st16, wall16, sizes16, a16 = run_lloyd_timed(ctx16, X, k, ids, args.steps, args.warmup, "bf16")
         s16 = summarize(st16, wall16, sizes16, corpus.nnz, corpus.n, "bf16")
         ctx16.close()

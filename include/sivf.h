@@ -104,6 +104,11 @@ typedef struct {
                                    walk reads for objects outside the ICP branch; 0
                                    disables.  Same results and mult-add counts either
                                    way (a memory layout choice, not the paper's). */
+    int32_t tiles_per_launch;   /* centroid tiles the walk covers per kernel launch;
+                                   0 (default) = 1: all objects walk tile 0, then
+                                   tile 1, ... so one tile's lists stay cache-
+                                   resident; a value >= the tile count walks every
+                                   tile of an object in one launch.  Same results. */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */

@@ -110,7 +110,7 @@ class Ivf:
 
 class Context:
     def __init__(self, device=0, posting_dtype="fp32", filter_mode="sivf", k_tile=0, certify=True,
-                 workspace_cap_bytes=0, stream=None, head_density=None):
+                 workspace_cap_bytes=0, stream=None, head_density=None, tiles_per_launch=None):
         lib = N.load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         idx = self.device.index if self.device.index is not None else 0
@@ -123,6 +123,8 @@ class Context:
         opt.workspace_cap_bytes = int(workspace_cap_bytes)
         if head_density is not None:
             opt.head_density = float(head_density)
+        if tiles_per_launch is not None:
+            opt.tiles_per_launch = int(tiles_per_launch)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

@@ -356,6 +356,7 @@ sivf_status sivf_default_options(sivf_options* opt) {
     opt->certify = 1;
     opt->workspace_cap_bytes = 0;
     opt->head_density = 0.5f;
+    opt->tiles_per_launch = 0;
     return SIVF_OK;
 }
 
@@ -369,6 +370,7 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     if (o.filter_mode < 0 || o.filter_mode > 2) return SIVF_E_INVALID;
     if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
     if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
+    if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
     sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
@@ -563,7 +565,9 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     uint8_t* changed = nullptr;
     double *obj_partial = nullptr, *obj = nullptr;
     const int nfin = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
-    STCHK(ws(ctx, "counters", 16, &counters));
+    const int tpl = std::min<int>(f->T, std::max<int>(1, ctx->opt.tiles_per_launch));
+    const int launches = (f->T + tpl - 1) / tpl;
+    STCHK(ws(ctx, "counters", 16 + launches, &counters));
     STCHK(ws(ctx, "a_new", n, &a_new));
     STCHK(ws(ctx, "own_new", n, &own_new));
     STCHK(ws(ctx, "qobj", qcap, &qobj));
@@ -605,18 +609,32 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.fobj = fobj;
     A.counters = counters;
     A.qcap = qcap;
+    A.st_theta = A.st_best = nullptr;
+    A.st_bj = A.st_cnt = A.st_cj = nullptr;
+    A.st_cr = nullptr;
+    if (launches > 1) {
+        const int64_t m = std::max<int64_t>(n, 1);
+        STCHK(ws(ctx, "st_theta", m, &A.st_theta));
+        STCHK(ws(ctx, "st_best", m, &A.st_best));
+        STCHK(ws(ctx, "st_bj", m, &A.st_bj));
+        STCHK(ws(ctx, "st_cnt", m, &A.st_cnt));
+        STCHK(ws(ctx, "st_cj", m * kCandCap, &A.st_cj));
+        STCHK(ws(ctx, "st_cr", m * kCandCap, &A.st_cr));
+    }
     A.head = f->H > 0 ? f->head : nullptr;
     A.hval = f->hval;
     A.kpad = (int64_t)f->T * f->kt;
     A.hbytes = f->H * A.kpad * (f->pdt == SIVF_BF16 ? 2 : 4);
 
     hipStream_t s = ctx->stream;
-    HIPCHK(ctx, fill_u64(counters, 0ull, 16, s));
+    HIPCHK(ctx, fill_u64(counters, 0ull, 16 + launches, s));
     HIPCHK(ctx, fill_u8(changed, 0, k, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
     if (n > 0) {
         const int bpc = walk_blocks_per_cu(f->kt, f->pdt == SIVF_BF16, A.cbicp);
-        HIPCHK(ctx, walk_fast(A, f->pdt == SIVF_BF16, ctx->n_cu * bpc * kWalkWaves, s));
+        for (int l = 0; l < launches; ++l)
+            HIPCHK(ctx, walk_fast(A, f->pdt == SIVF_BF16, ctx->n_cu * bpc * kWalkWaves, l * tpl,
+                                  std::min(f->T, (l + 1) * tpl), counters + 16 + l, s));
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     if (n > 0) {

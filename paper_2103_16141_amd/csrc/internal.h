@@ -69,13 +69,21 @@ struct WalkArgs {
     int32_t* qcnt;          // candidates per slot
     int32_t* fobj;          // full re-score queue: object ids
     unsigned long long* counters;  // [0] multadds [1] queue len [2] full len [3] icp objects
-                                   // [4] re-scored candidates [5] moved [6] invariant [8] work
+                                   // [4] re-scored candidates [5] moved [6] invariant
+                                   // [16 + launch] walk work counters
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)
     const int32_t* head;    // [d] row of each term, -1 if none
     const void* hval;       // [H * kpad] values in the posting dtype
     int64_t kpad;           // row length: T * kt
     int64_t hbytes;         // bytes of hval (< 2^32)
+    // per-object running state between launches over successive tile ranges
+    double* st_theta;       // [n] largest lower bound so far
+    double* st_best;        // [n] best lower bound (diagnostic argmax)
+    int32_t* st_bj;         // [n] its centroid
+    int32_t* st_cnt;        // [n] candidates (> kCandCap: overflowed)
+    int32_t* st_cj;         // [n * kCandCap] candidate ids
+    float* st_cr;           // [n * kCandCap] their fast-pass similarities
 };
 
 }  // namespace sivf
@@ -172,7 +180,9 @@ hipError_t store_export(const Store st, int32_t k, const int64_t* c_ptr, int32_t
                         hipStream_t s);
 
 // assignment
-hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, hipStream_t s);
+// walks tiles [tb, te) for every object; `work` is a zeroed grab counter
+hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, int tb, int te, unsigned long long* work,
+                     hipStream_t s);
 int walk_blocks_per_cu(int kt, int pdt_bf16, int cbicp);
 hipError_t rescore_candidates(const WalkArgs& a, const Store st, int64_t grid_waves, hipStream_t s);
 hipError_t rescore_full(const WalkArgs& a, const double* v64, const Store st, int64_t grid, hipStream_t s);

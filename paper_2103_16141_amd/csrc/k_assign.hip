@@ -232,7 +232,8 @@ __device__ inline void dense_accumulate(float* sim, const DBatch& b, int ub, int
 // fast pass
 // ---------------------------------------------------------------------------
 template <bool BF16, bool CB>
-__global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long long* __restrict__ work) {
+__global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long long* __restrict__ work, int tb,
+                                                   int te) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int kts = A.kt + 64;   // tile plus one spare slot per lane
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 icp = A.lam[a_old] != 0;
                 own_old = A.own_prev[i];
             }
-            icp_cnt += icp ? 1 : 0;
+            if (tb == 0) icp_cnt += icp ? 1 : 0;
             double xnorm = 0.0;
             if (!A.nonneg) {
                 double ss = 0.0;
@@ -276,9 +277,18 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
             double theta = -INFINITY;   // largest lower bound so far
             double best_lo = -INFINITY;
             int32_t best_j = 0x7fffffff;
-            int ccount = 0;
-            bool overflow = false;
-            if (icp) {
+            int ccount = 0;             // > kCandCap once the list has overflowed
+            if (tb > 0) {
+                // resume after the tiles of earlier launches
+                theta = A.st_theta[i];
+                best_lo = A.st_best[i];
+                best_j = A.st_bj[i];
+                ccount = A.st_cnt[i];
+                if (lane < min(ccount, kCandCap)) {
+                    cj[lane] = A.st_cj[i * kCandCap + lane];
+                    cr[lane] = A.st_cr[i * kCandCap + lane];
+                }
+            } else if (icp) {
                 double r = (double)own_old;
                 theta = r - bound_of(A, bd, r, a_old);
                 best_lo = theta;
@@ -289,6 +299,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 }
                 ccount = 1;
             }
+            bool overflow = ccount > kCandCap;
             const bool front_only = icp && !CB;
             const bool test_flag = icp && CB;
 
@@ -303,13 +314,14 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
             const int nch = max(1, (n + 63) >> 6);
-            const int npairs = A.T * nch;
+            const int npairs = (te - tb) * nch;
             int64_t ns0 = 0, ns1 = 0;
             int32_t nmv = 0;
             // segment bounds of pair pi, issued one pair ahead of their use
             auto seg_load = [&](int pi) {
-                const int tl = pi / nch;
-                const int h = (pi - tl * nch) * 64 + lane;
+                const int rel = pi / nch;   // tile index within this launch
+                const int tl = tb + rel;
+                const int h = (pi - rel * nch) * 64 + lane;
                 ns0 = 0;
                 ns1 = 0;
                 nmv = 0;
@@ -323,8 +335,8 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
             };
             seg_load(0);
             for (int pi = 0; pi < npairs; ++pi) {
-                const int tile = pi / nch;
-                const int ch = pi - tile * nch;
+                const int tile = tb + pi / nch;
+                const int ch = pi - (tile - tb) * nch;
                 const int32_t base = tile * A.kt;
                 const int32_t width = min(A.kt, A.k - base);
                 const int64_t s0 = ns0;
@@ -512,8 +524,20 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                     }
                 }
             }
-            // ---- decision
-            if (!A.certify) {
+            if (te < A.T) {
+                // later tiles follow in another launch: keep the running state
+                if (lane == 0) {
+                    A.st_theta[i] = theta;
+                    A.st_best[i] = best_lo;
+                    A.st_bj[i] = best_j;
+                    A.st_cnt[i] = ccount;
+                }
+                if (lane < min(ccount, kCandCap)) {
+                    A.st_cj[i * kCandCap + lane] = cj[lane];
+                    A.st_cr[i * kCandCap + lane] = cr[lane];
+                }
+            } else if (!A.certify) {
+                // ---- decision
                 if (lane == 0) {
                     A.a_new[i] = best_j;
                     float rb = 0.0f;
@@ -568,9 +592,8 @@ static const void* walk_kernel(int bf16, int cb) {
                 : (cb ? (const void*)k_walk_fast<false, true> : (const void*)k_walk_fast<false, false>);
 }
 
-hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, hipStream_t s) {
-    // the work counter lives right after the 8 counters
-    unsigned long long* work = a.counters + 8;
+hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, int tb, int te, unsigned long long* work,
+                     hipStream_t s) {
     const size_t lds = walk_lds_bytes(a.kt);
     int blocks = (grid_waves + kWalkWaves - 1) / kWalkWaves;
     if (blocks < 1) blocks = 1;
@@ -580,7 +603,7 @@ hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, hipStream_
         if (e != hipSuccess) return e;
     }
     WalkArgs args = a;
-    void* params[] = {&args, &work};
+    void* params[] = {&args, &work, &tb, &te};
     return hipLaunchKernel(fn, dim3(blocks), dim3(64 * kWalkWaves), params, lds, s);
 }
 

@@ -138,3 +138,22 @@ def test_dense_head_rows_same_trajectory(posting, k, k_tile):
     assert all(r == 0 for r in rows[0.0])
     assert max(rows[0.1]) > 0
     assert all(a >= b for a, b in zip(rows[0.1], rows[1.0]))
+
+
+@pytest.mark.parametrize("tiles_per_launch", [1, 2, 64])
+def test_tile_launch_split_with_ties_and_overflow(tiles_per_launch):
+    # 100 identical seeds spread over five 64-centroid tiles: objects near them
+    # carry more than kCandCap candidates across tile launches (overflow, then
+    # the FP64 re-score over all eligible centroids with lowest-index ties).
+    # One tile per launch, two, or all five in one launch: identical runs.
+    log("tile launches: %d tiles per launch" % tiles_per_launch)
+    c = synth.make_corpus(3000, 500, 20, 1.0, np.float64, seed=108)
+    rows = [c.col[c.row_ptr[i]:c.row_ptr[i + 1]] for i in range(c.n)]
+    vals = [c.val[c.row_ptr[i]:c.row_ptr[i + 1]] for i in range(c.n)]
+    for i in range(1, 100):
+        rows[i], vals[i] = rows[0], vals[0]
+    c2 = corpus_from_rows(rows, c.d, vals)
+    ids = list(range(100)) + [int(x) for x in synth.init_ids(2900, 200, 14) + 100]
+    ctx = _ctx(k_tile=64, tiles_per_launch=tiles_per_launch)
+    tr, st = lloyd_parity(ctx, _X(c2), c2, 300, ids, 6)
+    assert sum(s["full_rescored"] for s in st) > 0
