@@ -90,8 +90,8 @@ typedef struct {
     sivf_dtype posting_dtype;   /* SIVF_F32 (default) or SIVF_BF16 posting values */
     int32_t filter_mode;        /* sivf_filter_mode, default SIVF_MODE_SIVF */
     int32_t k_tile;             /* centroids per LDS similarity tile; 0 = automatic
-                                   (k split evenly into tiles of at most 2048 for
-                                   F32 postings, 1024 for BF16, rounded up to 64);
+                                   (k split evenly into tiles of at most 1024,
+                                   rounded up to a multiple of 64);
                                    otherwise a multiple of 64 in [64, 4096] */
     int32_t certify;            /* 1 (default): exact assignments (certificate + FP64
                                    re-score).  0: take the fast-pass argmax as is
