@@ -119,13 +119,14 @@ def test_run_lloyd_matches_stepwise_and_is_deterministic():
 
 
 @pytest.mark.parametrize("posting", ["fp32", "bf16"])
-@pytest.mark.parametrize("k,k_tile", [(200, 0), (600, 512)])
+@pytest.mark.parametrize("k,k_tile", [(200, 0), (600, 512), (1100, 1024), (700, 576), (1300, 1280)])
 def test_dense_head_rows_same_trajectory(posting, k, k_tile):
     # Dense head rows for terms held by >= 10% or by all centroids, or none at
     # all: every variant matches the oracle step by step (assignments, flags,
     # mult-add counts, centroids), and the rows are really read when enabled.
-    # k_tile 512 runs whole 512-centroid batches; the automatic tile (256 for
-    # k = 200) runs the masked tail of a batch.
+    # Rows are read in 512-centroid batches: tiles of 512 and 1024 take whole
+    # batches, 256 (automatic for k = 200), 576 and 1280 end in a batch that
+    # is partly outside the tile.
     log("dense head rows posting=%s k=%d k_tile=%d" % (posting, k, k_tile))
     c = synth.make_corpus(20000, 3000, 40, 1.1, np.float32, seed=104)
     ids = synth.init_ids(20000, k, 10)
