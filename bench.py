@@ -62,6 +62,65 @@ def measured_traffic():
     return None
 
 
+def measured_copy_gbs(gib=1, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time), HIP events."""
+    import torch
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def run_soft(reps=3):
+    """Differentiation form at its own shape (N = 262,144, D = 100,000,
+    Poisson(100), k = 4,096 dense centroids, tau = 0.05): forward (lse + loss)
+    and backward (dC, dX) timed with HIP events on the library's stream."""
+    import torch
+
+    import synth
+    from paper_2103_16141_amd.api import Context, DeviceCsr
+    corpus, ids, w = synth.workload("soft-262k")
+    C = torch.from_numpy(synth.dense_centroids(corpus, ids, noise=1e-3, seed=2103 + 5)).cuda()
+    X = DeviceCsr.from_corpus(corpus, torch.device("cuda", 0))
+    ctx = Context(0)
+    tau = 0.05
+    lse, _ = ctx.soft_assign_fwd(X, C, tau)
+    ctx.soft_assign_bwd(X, C, tau, lse, 1.0)   # warm: the backward's transposes and CSC
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, bwd = [], []
+    for _ in range(reps):
+        ev[0].record()
+        lse, loss = ctx.soft_assign_fwd(X, C, tau)
+        ev[1].record()
+        dC, dX = ctx.soft_assign_bwd(X, C, tau, lse, 1.0)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd.append(ev[0].elapsed_time(ev[1]))
+        bwd.append(ev[1].elapsed_time(ev[2]))
+    ctx.close()
+    k = C.shape[0]
+    ma = corpus.nnz * k   # mult-adds of one S = X C^T pass
+    f, b = min(fwd), min(bwd)
+    out = dict(workload="soft-assignment loss, N=%d, D=%d, nnz=%d, k=%d dense centroids, tau=%g"
+                        % (corpus.n, corpus.d, corpus.nnz, k, tau),
+               fwd_ms=f, bwd_ms=b, s_pass_multadds=ma, fwd_multadds_per_s=ma / (f * 1e-3),
+               bwd_multadds_per_s=3 * ma / (b * 1e-3), loss=loss)
+    del C, X, dC, dX, lse
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(gib=1):
     """A plain device-to-device copy of a known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters (one kernel launch per copy)."""
@@ -176,6 +235,7 @@ def main():
                     help="dense head rows for terms held by at least this fraction of centroids (default: library's)")
     ap.add_argument("--tiles-per-launch", type=int, default=None,
                     help="centroid tiles per walk launch (default: library's, one tile per launch)")
+    ap.add_argument("--skip-soft", action="store_true", help="skip the differentiation-form timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 copies of 1 GiB (counter calibration for the traffic figure)")
     ap.add_argument("--print-walk-hash", action="store_true", help="print the walk kernel source hash and exit")
@@ -225,11 +285,23 @@ def main():
                         rescored_objects=s16["rescored_objects"], full_rescored=s16["full_rescored"],
                         identical_trajectory=same, vs_fp32=s16["multadds_per_s"] / s32["multadds_per_s"])
 
+    soft = None
+    if not args.skip_soft and args.n is None:
+        del X
+        torch.cuda.empty_cache()
+        soft = run_soft()
+        log("soft form: fwd %.2f ms, bwd %.2f ms" % (soft["fwd_ms"], soft["bwd_ms"]))
+    copy_gbs = measured_copy_gbs()
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(corpus, ids, k, args.cpu_budget)
 
     achieved = s32["walk_algorithmic_gbs"]
+    # the walk is one kernel launch per group of tiles_per_launch centroid tiles
+    tpl = max(1, args.tiles_per_launch or 1)
+    launches = len(st32) * ((sizes["n_tiles"] + tpl - 1) // tpl)
+    launch_ms = s32["walk_s"] * 1e3 / launches
     line = {
         "metric": "assign-step object-centroid mult-adds/s (FP32 postings) + s/iter at N=8M, k=10k; BF16 vs FP32",
         "value": s32["multadds_per_s"],
@@ -255,7 +327,10 @@ def main():
         "bf16": out_bf16,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": WALK_KERNEL, "walk_avg_ms": s32["walk_avg_ms"]},
+                     "kernel": WALK_KERNEL, "launches": launches, "launch_avg_ms": launch_ms,
+                     "algorithmic_bytes_per_launch": achieved * 1e9 * launch_ms * 1e-3,
+                     "walk_avg_ms_per_iter": s32["walk_avg_ms"], "measured_copy_gbs": copy_gbs},
+        "soft": soft,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
