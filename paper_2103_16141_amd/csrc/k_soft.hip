@@ -24,6 +24,7 @@ constexpr int kSoftThreads = 256;
 constexpr int kSoftCols = 16;                       // columns per thread per chunk
 constexpr int kSoftChunk = kSoftThreads * kSoftCols;  // 4096 columns per chunk
 constexpr int kSoftTermsInLds = 256;                // row entries staged per pass
+constexpr int kDctRows = 4;                         // dS rows in flight per dC step
 
 // ---------------------------------------------------------------- transpose
 // out[c][r] = in[r][c] for an R x Cn row-major matrix; 64x64 tiles via LDS.
@@ -212,17 +213,46 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
                 if (c < k) dsrow[c] = ds[q];
             }
             // dX contribution of this column chunk
+            const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
             for (int h0 = 0; h0 < n; h0 += 16) {
                 const int m = min(16, n - h0);
                 float pd[16];
+                if (full) {
+                    // four terms' rows in flight, then their dots in column order
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    pd[e] = 0.0f;
-                    if (e < m) {
-                        const float* row = CT + (int64_t)col[r0 + h0 + e] * k + ch0;
+                    for (int e0 = 0; e0 < 16; e0 += 4) {
+                        float4 g[4][4];
 #pragma unroll
-                        for (int q = 0; q < kSoftCols; ++q)
-                            if (ch0 + soft_col(q) < k) pd[e] = fmaf(ds[q], row[soft_col(q)], pd[e]);
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = e0 + u;
+                            const float* row = CT + (int64_t)col[r0 + h0 + (e < m ? e : 0)] * k + ch0;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                g[u][q] = *reinterpret_cast<const float4*>(row + q * (kSoftThreads * 4) + threadIdx.x * 4);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            float a = 0.0f;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                a = fmaf(ds[4 * q + 0], g[u][q].x, a);
+                                a = fmaf(ds[4 * q + 1], g[u][q].y, a);
+                                a = fmaf(ds[4 * q + 2], g[u][q].z, a);
+                                a = fmaf(ds[4 * q + 3], g[u][q].w, a);
+                            }
+                            pd[e0 + u] = e0 + u < m ? a : 0.0f;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        pd[e] = 0.0f;
+                        if (e < m) {
+                            const float* row = CT + (int64_t)col[r0 + h0 + e] * k + ch0;
+#pragma unroll
+                            for (int q = 0; q < kSoftCols; ++q)
+                                if (ch0 + soft_col(q) < k) pd[e] = fmaf(ds[q], row[soft_col(q)], pd[e]);
+                        }
                     }
                 }
                 __syncthreads();
@@ -362,12 +392,49 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_dct(int64_t d, int32_t k,
                 const int64_t c = ch0 + soft_col(q);
                 acc[q] = (first || c >= k) ? 0.0f : out[soft_col(q)];
             }
-            for (int64_t p = lo; p < hi; ++p) {
-                const float v = xt_val[p];
-                const float* row = dS + (int64_t)(xt_row[p] - c0) * k + ch0;
+            const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
+            if (full) {
+                // kDctRows rows per step: their ids, then all their gathers, are
+                // issued before the first multiply-add, which still runs in
+                // ascending row order
+                for (int64_t p0 = lo; p0 < hi; p0 += kDctRows) {
+                    const int m = (int)min((int64_t)kDctRows, hi - p0);
+                    int64_t ro[kDctRows];
+                    float vv[kDctRows];
 #pragma unroll
-                for (int q = 0; q < kSoftCols; ++q)
-                    if (ch0 + soft_col(q) < k) acc[q] = fmaf(v, row[soft_col(q)], acc[q]);
+                    for (int u = 0; u < kDctRows; ++u) {
+                        const bool in = u < m;
+                        ro[u] = (int64_t)(xt_row[in ? p0 + u : p0] - c0) * k + ch0;
+                        vv[u] = in ? xt_val[p0 + u] : 0.0f;
+                    }
+                    float4 g[kDctRows][4];
+#pragma unroll
+                    for (int u = 0; u < kDctRows; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            g[u][q] = *reinterpret_cast<const float4*>(dS + ro[u] + q * (kSoftThreads * 4) +
+                                                                      threadIdx.x * 4);
+#pragma unroll
+                    for (int u = 0; u < kDctRows; ++u) {
+                        if (u < m) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                acc[4 * q + 0] = fmaf(vv[u], g[u][q].x, acc[4 * q + 0]);
+                                acc[4 * q + 1] = fmaf(vv[u], g[u][q].y, acc[4 * q + 1]);
+                                acc[4 * q + 2] = fmaf(vv[u], g[u][q].z, acc[4 * q + 2]);
+                                acc[4 * q + 3] = fmaf(vv[u], g[u][q].w, acc[4 * q + 3]);
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (int64_t p = lo; p < hi; ++p) {
+                    const float v = xt_val[p];
+                    const float* row = dS + (int64_t)(xt_row[p] - c0) * k + ch0;
+#pragma unroll
+                    for (int q = 0; q < kSoftCols; ++q)
+                        if (ch0 + soft_col(q) < k) acc[q] = fmaf(v, row[soft_col(q)], acc[q]);
+                }
             }
 #pragma unroll
             for (int q = 0; q < kSoftCols; ++q)
