@@ -236,6 +236,11 @@ def main():
     ap.add_argument("--tiles-per-launch", type=int, default=None,
                     help="centroid tiles per walk launch (default: library's, one tile per launch)")
     ap.add_argument("--skip-soft", action="store_true", help="skip the differentiation-form timing")
+    ap.add_argument("--icp-head-moving", type=float, default=None,
+                    help="ICP objects read head rows in tiles with at least this moving fraction (default: library's)")
+    ap.add_argument("--filter", default="sivf", choices=["sivf", "ivf", "cbicp"],
+                    help="ICP realisation: structured file (SIVF), none (IVF), per-posting test (IVF-CBICP)")
+    ap.add_argument("--workload", default="8m-f32", help="synthetic workload name (8m-f32, 8m-bf16-k20k, 1m-f32)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 copies of 1 GiB (counter calibration for the traffic figure)")
     ap.add_argument("--print-walk-hash", action="store_true", help="print the walk kernel source hash and exit")
@@ -260,7 +265,7 @@ def main():
     _native.load()
     over = {} if args.n is None else {"n": args.n}
     t0 = time.perf_counter()
-    corpus, ids, w = synth.workload("8m-f32", **over)
+    corpus, ids, w = synth.workload(args.workload, **over)
     log("corpus N=%d D=%d nnz=%d generated in %.1f s (%d threads)" % (corpus.n, corpus.d, corpus.nnz,
                                                                     time.perf_counter() - t0, synth.num_threads()))
     dev = torch.device("cuda", 0)
@@ -269,14 +274,16 @@ def main():
     k = w["k"]
 
     ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile, head_density=args.head_density,
-                    tiles_per_launch=args.tiles_per_launch)
+                    tiles_per_launch=args.tiles_per_launch, filter_mode=args.filter,
+                    icp_head_moving=args.icp_head_moving)
     st32, wall32, sizes, a32 = run_lloyd_timed(ctx32, X, k, ids, args.steps, args.warmup, "fp32")
     s32 = summarize(st32, wall32, sizes, corpus.nnz, corpus.n, "fp32")
     ctx32.close()
     out_bf16 = None
     if not args.skip_bf16:
         ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile, head_density=args.head_density,
-                    tiles_per_launch=args.tiles_per_launch)
+                    tiles_per_launch=args.tiles_per_launch, filter_mode=args.filter,
+                    icp_head_moving=args.icp_head_moving)
         st16, wall16, sizes16, a16 = run_lloyd_timed(ctx16, X, k, ids, args.steps, args.warmup, "bf16")
         s16 = summarize(st16, wall16, sizes16, corpus.nnz, corpus.n, "bf16")
         ctx16.close()
@@ -303,7 +310,7 @@ def main():
     launches = len(st32) * ((sizes["n_tiles"] + tpl - 1) // tpl)
     launch_ms = s32["walk_s"] * 1e3 / launches
     line = {
-        "metric": "assign-step object-centroid mult-adds/s (FP32 postings) + s/iter at N=8M, k=10k; BF16 vs FP32",
+        "metric": "assign-step object-centroid mult-adds/s + s/iter at N=8M,k=10k; BF16 vs FP32",
         "value": s32["multadds_per_s"],
         "unit": "mult-adds/s",
         "n_gpus": 1,
@@ -319,7 +326,9 @@ def main():
                                "lognormal values, L2-normalised rows, k=%d seeded initial objects"
                                % (corpus.n, corpus.d, w["lam"], w["zipf_s"], k),
                    "n": corpus.n, "d": corpus.d, "k": k, "nnz": corpus.nnz, "k_tile": sizes["k_tile"],
-                   "n_tiles": sizes["n_tiles"], "filter": "SIVF (ICP via structured file)"},
+                   "n_tiles": sizes["n_tiles"],
+                   "filter": {"sivf": "SIVF (ICP via structured file)", "ivf": "IVF (no ICP)",
+                              "cbicp": "IVF-CBICP (ICP by per-posting flag test)"}[args.filter]},
         "s_per_iter": s32["s_per_iter"],
         "iter1_multadds_per_s": s32["iter1_multadds_per_s"],
         "assign_s": s32["assign_s"], "update_s": s32["update_s"],

@@ -109,6 +109,12 @@ typedef struct {
                                    tile 1, ... so one tile's lists stay cache-
                                    resident; a value >= the tile count walks every
                                    tile of an object in one launch.  Same results. */
+    float icp_head_moving;      /* in [0, 2]; default 0.25.  Objects in the ICP branch
+                                   read the dense head rows (all centroids; the
+                                   invariant ones are not eligible for them) in tiles
+                                   where at least this fraction of the centroids is
+                                   moving, else the moving part of the lists; > 1
+                                   never.  Same results and mult-add counts. */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */

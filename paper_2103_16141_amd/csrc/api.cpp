@@ -252,6 +252,7 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     dev_free(ctx, f->lam, (size_t)f->k, &f->bytes);
     dev_free(ctx, f->cnorm, (size_t)f->k * 8, &f->bytes);
     dev_free(ctx, f->head, (size_t)f->d * 4, &f->bytes);
+    dev_free(ctx, f->icp_head, (size_t)f->T, &f->bytes);
     dev_free(ctx, f->hval, (size_t)f->hcap * f->T * f->kt * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
     delete f;
 }
@@ -273,6 +274,7 @@ sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->lam, (size_t)k, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->cnorm, (size_t)k * 8, &f->bytes);
     if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->head, (size_t)d * 4, &f->bytes);
+    if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->icp_head, (size_t)f->T, &f->bytes);
     if (st != SIVF_OK) {
         free_file(ctx, f);
         return st;
@@ -336,6 +338,7 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
                 f->hcap = c;
             }
             HIPCHK(ctx, head_fill(f->cur, f->k, f->head, kpad, H, f->pdt == SIVF_BF16, f->hval, ctx->stream));
+            HIPCHK(ctx, head_icp_tiles(f->lam, f->k, f->kt, f->T, ctx->opt.icp_head_moving, f->icp_head, ctx->stream));
             f->H = H;
         }
     }
@@ -357,6 +360,7 @@ sivf_status sivf_default_options(sivf_options* opt) {
     opt->workspace_cap_bytes = 0;
     opt->head_density = 0.5f;
     opt->tiles_per_launch = 0;
+    opt->icp_head_moving = 0.25f;
     return SIVF_OK;
 }
 
@@ -371,6 +375,7 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
     if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
     if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
+    if (!(o.icp_head_moving >= 0.0f && o.icp_head_moving <= 2.0f)) return SIVF_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
     sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
@@ -622,6 +627,7 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
         STCHK(ws(ctx, "st_cr", m * kCandCap, &A.st_cr));
     }
     A.head = f->H > 0 ? f->head : nullptr;
+    A.icp_head = f->icp_head;
     A.hval = f->hval;
     A.kpad = (int64_t)f->T * f->kt;
     A.hbytes = f->H * A.kpad * (f->pdt == SIVF_BF16 ? 2 : 4);

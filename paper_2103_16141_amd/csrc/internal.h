@@ -74,6 +74,7 @@ struct WalkArgs {
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)
     const int32_t* head;    // [d] row of each term, -1 if none
+    const uint8_t* icp_head;  // [T] 1: objects in the ICP branch read head rows in this tile too
     const void* hval;       // [H * kpad] values in the posting dtype
     int64_t kpad;           // row length: T * kt
     int64_t hbytes;         // bytes of hval (< 2^32)
@@ -102,6 +103,7 @@ struct sivf_ivf {
     double* v64 = nullptr;          // [pcap] FP64 values (exact re-score over whole lists)
     int64_t P = 0, pcap = 0;
     int32_t* head = nullptr;        // [d] dense head row of each term, -1 if none
+    uint8_t* icp_head = nullptr;    // [T] 1: objects in the ICP branch read head rows in this tile
     void* hval = nullptr;           // [hcap * kpad] dense head rows, posting dtype
     int64_t H = 0, hcap = 0;        // head rows in use / allocated
     uint8_t* lam = nullptr;         // [k]
@@ -172,6 +174,8 @@ hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T,
 // dense head rows: flag[t] = 1 if term t's lists hold >= min_len postings
 hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s);
 hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s);
+hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, float min_moving, uint8_t* icp_ok,
+                          hipStream_t s);
 hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int64_t H, int pdt_bf16,
                      void* hval, hipStream_t s);
 hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val,

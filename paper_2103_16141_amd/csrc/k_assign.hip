@@ -356,11 +356,13 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 // buffer descriptors made per list: the lane offset is a
                 // constant, the batch offset is scalar, and lanes past the
                 // list's end read 0 from the hardware range check.
-                // ---- head terms (outside the ICP branch): dense rows, in
+                // ---- head terms: dense rows (in the ICP branch only in tiles
+                // where most centroids move; the rest cannot win there), in
                 // ascending term order, 512 centroids per batch, next batch in
                 // flight while the current one is accumulated
                 int hrow = -1;
-                if (A.head && !icp && h < n) hrow = h < kTermCap ? th[h] : A.head[A.col[r0 + h]];
+                const bool use_head = A.head && (!icp || (!CB && A.icp_head[tile]));
+                if (use_head && h < n) hrow = h < kTermCap ? th[h] : A.head[A.col[r0 + h]];
                 unsigned long long dl = ballot(hrow >= 0);
                 if (dl) {
                     int q = __builtin_ctzll(dl);

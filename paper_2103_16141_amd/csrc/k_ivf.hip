@@ -16,6 +16,8 @@
 // part) segment is a popcount of lower bits, so every part comes out in
 // ascending centroid id regardless of thread timing (Alg. 5 fills in ascending
 // j the same way).
+#include <algorithm>
+
 #include "internal.h"
 #include "wave.h"
 
@@ -190,6 +192,32 @@ __global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ 
             }
         }
     }
+}
+
+// icp_ok[tile] = 1 when at least min_moving of the tile's centroids are moving
+// (flag 0): objects in the ICP branch then read head rows there too (the
+// invariant centroids' partial sums are never eligible for them).
+__global__ void k_head_icp_tiles(const uint8_t* __restrict__ lam, int32_t k, int32_t kt, int32_t T, float min_moving,
+                                 uint8_t* __restrict__ icp_ok) {
+    __shared__ int cnt;
+    for (int32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        const int32_t b = tile * kt, w = min(kt, k - b);
+        int mine = 0;
+        for (int32_t c = threadIdx.x; c < w; c += blockDim.x) mine += lam[b + c] ? 0 : 1;
+        atomicAdd(&cnt, mine);
+        __syncthreads();
+        if (threadIdx.x == 0) icp_ok[tile] = (float)cnt >= min_moving * (float)w ? 1 : 0;
+        __syncthreads();
+    }
+}
+
+hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, float min_moving, uint8_t* icp_ok,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_head_icp_tiles, dim3((unsigned)std::min<int32_t>(T, 4096)), dim3(256), 0, s, lam, k, kt, T,
+                       min_moving, icp_ok);
+    return hipGetLastError();
 }
 
 hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s) {

@@ -158,3 +158,20 @@ def test_tile_launch_split_with_ties_and_overflow(tiles_per_launch):
     ctx = _ctx(k_tile=64, tiles_per_launch=tiles_per_launch)
     tr, st = lloyd_parity(ctx, _X(c2), c2, 300, ids, 6)
     assert sum(s["full_rescored"] for s in st) > 0
+
+
+@pytest.mark.parametrize("posting", ["fp32", "bf16"])
+def test_icp_objects_reading_head_rows(posting):
+    # Objects in the ICP branch read the dense head rows in every tile (0),
+    # in tiles where at least half the centroids move (0.5) or
+    # never (2): identical trajectories, flags and mult-add counts.
+    log("ICP objects and head rows, posting=%s" % posting)
+    c = synth.make_corpus(20000, 3000, 40, 1.1, np.float32, seed=110)
+    ids = synth.init_ids(20000, 400, 16)
+    icp_seen = 0
+    for m in (0.0, 0.5, 2.0):
+        ctx = _ctx(k_tile=128, posting_dtype=posting, head_density=0.2, icp_head_moving=m)
+        tr, st = lloyd_parity(ctx, _X(c), c, 400, ids, 12, check_ivf_every=4)
+        icp_seen = max(icp_seen, sum(s["icp_objects"] for s in st))
+        ctx.close()
+    assert icp_seen > 0
