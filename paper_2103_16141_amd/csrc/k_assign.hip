@@ -461,19 +461,41 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                     // ---- tile epilogue: bounds, running theta, candidates; clears the tile
                     double tmax = -INFINITY;
                     int32_t tj = 0x7fffffff;
-                    for (int jj = lane; jj < width; jj += 64) {
-                        const int32_t j = base + jj;
-                        const bool elig = !icp || A.lam[j] == 0;
-                        if (elig) {
-                            const double r = (double)sim[jj];
-                            const double lo = r - bound_of(A, bd, r, j);
-                            if (lo > tmax) {
-                                tmax = lo;
-                                tj = j;
+                    if (A.nonneg) {
+                        // lower and upper bounds are non-decreasing in r (the bound is
+                        // a fixed multiple of |r| plus a constant): the tile's largest
+                        // lower bound is that of its largest eligible r
+                        float rmax = -INFINITY;
+                        int32_t rj = 0x7fffffff;
+                        for (int jj = lane; jj < width; jj += 64) {
+                            const int32_t j = base + jj;
+                            const float r = sim[jj];
+                            if ((!icp || A.lam[j] == 0) && r > rmax) {
+                                rmax = r;
+                                rj = j;
                             }
                         }
+                        double rm = (double)rmax;
+                        wave_argmax(rm, rj);
+                        if (rj != 0x7fffffff) {
+                            tmax = rm - bound_of(A, bd, rm, rj);
+                            tj = rj;
+                        }
+                    } else {
+                        for (int jj = lane; jj < width; jj += 64) {
+                            const int32_t j = base + jj;
+                            const bool elig = !icp || A.lam[j] == 0;
+                            if (elig) {
+                                const double r = (double)sim[jj];
+                                const double lo = r - bound_of(A, bd, r, j);
+                                if (lo > tmax) {
+                                    tmax = lo;
+                                    tj = j;
+                                }
+                            }
+                        }
+                        wave_argmax(tmax, tj);
                     }
-                    wave_argmax(tmax, tj);
                     if (tmax > best_lo || (tmax == best_lo && tj < best_j)) {
                         best_lo = tmax;
                         best_j = tj;
@@ -500,6 +522,15 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                             ccount = __popcll(km);
                         }
                     }
+                    // nonnegative data: r below rlow cannot reach theta (the upper
+                    // bound r + B(r) is below theta there, with margin for the
+                    // rounding of this test), so only the others take the FP64 test
+                    float rlow = -INFINITY;
+                    if (A.nonneg && theta > -INFINITY) {
+                        const double t = (theta - bd.absl * (1.0 + 0x1p-50)) /
+                                         ((1.0 + bd.crel + 0x1p-50) * (1.0 + 0x1p-50)) * (1.0 - 0x1p-45);
+                        rlow = __double2float_rd(t);
+                    }
                     for (int jj0 = 0; jj0 < width; jj0 += 64) {
                         const int jj = jj0 + lane;
                         bool take = false;
@@ -508,7 +539,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                             const int32_t j = base + jj;
                             r32 = sim[jj];
                             sim[jj] = 0.0f;
-                            if (!icp || A.lam[j] == 0) {
+                            if (r32 >= rlow && (!icp || A.lam[j] == 0)) {
                                 const double r = (double)r32;
                                 take = r + bound_of(A, bd, r, j) >= theta;
                             }
