@@ -122,6 +122,8 @@ WORKLOADS = {
     "8m-f32": dict(n=8_000_000, d=140_000, lam=90, zipf_s=1.1, dtype=np.float32, k=10_000, iters=30, c=3),
     "8m-bf16-k20k": dict(n=8_000_000, d=140_000, lam=90, zipf_s=1.1, dtype=np.float32, k=20_000, iters=30, c=4),
     "soft-262k": dict(n=262_144, d=100_000, lam=100, zipf_s=1.1, dtype=np.float32, k=4_096, iters=1, c=5),
+    # second corpus shape the paper uses (NYT articles: N, D and mean nonzeros per row)
+    "nyt-f32": dict(n=1_285_944, d=495_714, lam=226, zipf_s=1.1, dtype=np.float32, k=10_000, iters=30, c=6),
 }
 
 

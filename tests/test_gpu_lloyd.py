@@ -100,6 +100,16 @@ def test_long_rows_over_64_terms():
     lloyd_parity(_ctx(k_tile=64), _X(c), c, 80, ids, 6)
 
 
+def test_rows_longer_than_the_staged_terms():
+    # rows of ~300 terms: terms past the 256 staged in LDS are read from X
+    log("edge: rows longer than 256 terms")
+    c = synth.make_corpus(1500, 4000, 300, 0.9, np.float32, seed=111)
+    assert np.diff(c.row_ptr).max() > 256
+    ids = synth.init_ids(1500, 60, 17)
+    for posting in ("fp32", "bf16"):
+        lloyd_parity(_ctx(k_tile=64, posting_dtype=posting, head_density=0.3), _X(c), c, 60, ids, 6)
+
+
 def test_run_lloyd_matches_stepwise_and_is_deterministic():
     log("run_lloyd determinism")
     c = synth.make_corpus(8000, 3000, 30, 1.1, np.float32, seed=107)
