@@ -42,7 +42,7 @@ def _bind(path):
     i32, i64, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     ci = ctypes.c_int
     lib.orc_assign.argtypes = [i64, i64, vp, vp, vp, ci, i32, vp, vp, vp, vp, i64, ci, vp, vp, vp,
-                               vp, vp, vp]
+                               ci, vp, vp, vp, vp]
     lib.orc_assign.restype = ci
     lib.orc_pair_sims.argtypes = [i64, vp, vp, vp, ci, vp, vp, vp, vp, vp, i64, vp]
     lib.orc_pair_sims.restype = ci
@@ -50,7 +50,7 @@ def _bind(path):
     lib.orc_update.restype = i64
     lib.orc_build_ivf.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.orc_build_ivf.restype = ci
-    lib.orc_multadds.argtypes = [i64, vp, vp, vp, vp, vp, ci, vp, vp, ci, vp, vp]
+    lib.orc_multadds.argtypes = [i64, vp, vp, vp, vp, vp, ci, vp, vp, ci, vp, vp, vp]
     lib.orc_multadds.restype = ci
     lib.orc_soft_forward.argtypes = [i64, vp, vp, vp, ci, i32, vp, f64, vp, i64, vp]
     lib.orc_soft_forward.restype = ci
@@ -124,8 +124,10 @@ def init_centroids(corpus, ids) -> Centroids:
                      np.ascontiguousarray(val, np.float64))
 
 
-def assign(corpus, cents: Centroids, rows=None, icp=False, lam_prev=None, a_prev=None, own_prev=None):
-    """Returns (a, own, top2) for the selected rows (all rows if None)."""
+def assign(corpus, cents: Centroids, rows=None, icp=False, lam_prev=None, a_prev=None, own_prev=None,
+           relaxed=False, want_branch=False):
+    """Returns (a, own, top2) for the selected rows (all rows if None), and the
+    branch each row took (0 all centroids, 1 ICP, 2 relaxed ICP) if want_branch."""
     lib = _load()
     val, f64 = _xval(corpus)
     rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
@@ -136,12 +138,14 @@ def assign(corpus, cents: Centroids, rows=None, icp=False, lam_prev=None, a_prev
     lam_prev = None if lam_prev is None else np.ascontiguousarray(lam_prev, np.uint8)
     a_prev = None if a_prev is None else np.ascontiguousarray(a_prev, np.int32)
     own_prev = None if own_prev is None else np.ascontiguousarray(own_prev, np.float64)
+    branch = np.empty(m, dtype=np.uint8)
     rc = lib.orc_assign(corpus.n, corpus.d, _p(corpus.row_ptr), _p(corpus.col), _p(val), f64, cents.k,
                         _p(cents.ptr), _p(cents.col), _p(cents.val), _p(rows_a), m, 1 if icp else 0,
-                        _p(lam_prev), _p(a_prev), _p(own_prev), _p(a), _p(own), _p(top2))
+                        _p(lam_prev), _p(a_prev), _p(own_prev), 1 if relaxed else 0, _p(a), _p(own), _p(top2),
+                        _p(branch))
     if rc != 0:
         raise RuntimeError("orc_assign failed (%d)" % rc)
-    return a, own, top2
+    return (a, own, top2, branch) if want_branch else (a, own, top2)
 
 
 def pair_sims(corpus, cents: Centroids, obj, cen) -> np.ndarray:
@@ -196,15 +200,16 @@ def build_ivf(cents: Centroids, lam=None) -> Ivf:
 MODE_SIVF, MODE_CBICP, MODE_IVF = 0, 1, 2
 
 
-def multadds(corpus, ivf: Ivf, icp=False, lam_prev=None, a_prev=None, mode=MODE_SIVF, per_row=False):
+def multadds(corpus, ivf: Ivf, icp=False, lam_prev=None, a_prev=None, mode=MODE_SIVF, per_row=False, branch=None):
     lib = _load()
     total = np.zeros(1, dtype=np.int64)
     pr = np.empty(corpus.n, dtype=np.int64) if per_row else None
     lam_prev = None if lam_prev is None else np.ascontiguousarray(lam_prev, np.uint8)
     a_prev = None if a_prev is None else np.ascontiguousarray(a_prev, np.int32)
     cid = ivf.cid if len(ivf.cid) else np.zeros(1, np.int32)
+    branch = None if branch is None else np.ascontiguousarray(branch, np.uint8)
     lib.orc_multadds(corpus.n, _p(corpus.row_ptr), _p(corpus.col), _p(ivf.term_ptr), _p(ivf.split),
-                     _p(cid), 1 if icp else 0, _p(lam_prev), _p(a_prev), mode, _p(pr), _p(total))
+                     _p(cid), 1 if icp else 0, _p(lam_prev), _p(a_prev), mode, _p(branch), _p(pr), _p(total))
     return (int(total[0]), pr) if per_row else int(total[0])
 
 
@@ -235,18 +240,21 @@ class LloydTrace:
     lam: list = field(default_factory=list)          # lambda^[r]
     moved: list = field(default_factory=list)
     multadds: list = field(default_factory=list)     # SIVF posting mult-adds of assignment step r
+    branch: list = field(default_factory=list)       # per object: 0 all centroids, 1 ICP, 2 relaxed ICP
     centroids: list = field(default_factory=list)    # mu^[r-1] used by assignment r (if keep_centroids)
     final: Centroids | None = None                   # centroids after the last update
     iters: int = 0
     converged: bool = False
 
 
-def lloyd(corpus, k, ids, max_iter, icp=True, keep_centroids=False, count_multadds=True):
+def lloyd(corpus, k, ids, max_iter, icp=True, keep_centroids=False, count_multadds=True, relaxed=False):
     """Spherical Lloyd with SIVF bookkeeping (Alg. 1 driver around Alg. 4 / Alg. 5).
 
-    Iteration r: assignment against mu^[r-1] (ICP mode from r >= 2 when icp),
-    invariance flags lambda^[r], stop after an assignment step r >= 2 that moved
-    nothing, else update to mu^[r].
+    Iteration r: assignment against mu^[r-1] (ICP mode from r >= 2 when icp;
+    with relaxed, also objects whose own centroid moved without their
+    similarity to it decreasing compare moving centroids only), invariance
+    flags lambda^[r], stop after an assignment step r >= 2 that moved nothing,
+    else update to mu^[r].
     """
     cents = init_centroids(corpus, ids)
     tr = LloydTrace()
@@ -255,10 +263,13 @@ def lloyd(corpus, k, ids, max_iter, icp=True, keep_centroids=False, count_multad
         if keep_centroids:
             tr.centroids.append(cents)
         use_icp = icp and r >= 2
-        a, own, _ = assign(corpus, cents, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev, own_prev=own_prev)
+        a, own, _, branch = assign(corpus, cents, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev, own_prev=own_prev,
+                                   relaxed=relaxed, want_branch=True)
+        tr.branch.append(branch)
         if count_multadds:
             ivf = build_ivf(cents, lam_prev)
-            tr.multadds.append(multadds(corpus, ivf, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev))
+            tr.multadds.append(multadds(corpus, ivf, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev,
+                                        branch=branch if use_icp else None))
         lam, moved = mark_invariant(a_prev, a, k, first=(r == 1))
         tr.assign.append(a)
         tr.own.append(own)

@@ -65,8 +65,8 @@ int orc_num_threads(void) {
 int orc_assign(int64_t n, int64_t d, const int64_t* rp, const int32_t* col, const void* val,
                int val_f64, int32_t k, const int64_t* cp, const int32_t* ccol, const double* cval,
                const int64_t* rows, int64_t n_rows, int icp, const uint8_t* lam_prev,
-               const int32_t* a_prev, const double* own_prev, int32_t* a_out, double* own_out,
-               double* top2_out) {
+               const int32_t* a_prev, const double* own_prev, int relaxed, int32_t* a_out, double* own_out,
+               double* top2_out, uint8_t* branch_out) {
     if (n < 0 || d < 1 || k < 1) return -1;
     int64_t m = rows ? n_rows : n;
     /* dense transposed centroids restricted to the terms the processed rows use */
@@ -100,9 +100,28 @@ int orc_assign(int64_t n, int64_t d, const int64_t* rp, const int32_t* col, cons
                 for (int32_t j = 0; j < k; ++j) acc[j] = acc[j] + v * u[j];
             }
             int use_icp = icp && lam_prev && a_prev && own_prev && lam_prev[a_prev[i]];
+            /* relaxed ICP (Section 2.1): the own centroid moved, but the object's
+             * similarity to it did not decrease, so no invariant centroid can
+             * overtake it; only moving centroids are compared, from the own one */
+            int use_rel = !use_icp && icp && relaxed && lam_prev && a_prev && own_prev &&
+                          acc[a_prev[i]] >= own_prev[i];
             double best, second = -INFINITY;
             int32_t bj;
-            if (use_icp) {
+            if (use_rel) {
+                bj = a_prev[i];
+                best = acc[bj];
+                for (int32_t j = 0; j < k; ++j) {
+                    if (lam_prev[j] || j == bj) continue;
+                    double r = acc[j];
+                    if (r > best || (r == best && j < bj)) {
+                        second = best;
+                        best = r;
+                        bj = j;
+                    } else if (r > second) {
+                        second = r;
+                    }
+                }
+            } else if (use_icp) {
                 best = own_prev[i];
                 bj = a_prev[i];
                 for (int32_t j = 0; j < k; ++j) {
@@ -131,6 +150,7 @@ int orc_assign(int64_t n, int64_t d, const int64_t* rp, const int32_t* col, cons
                 }
             }
             a_out[q] = bj;
+            if (branch_out) branch_out[q] = (uint8_t)(use_icp ? 1 : use_rel ? 2 : 0);
             if (own_out) own_out[q] = best;
             if (top2_out) { top2_out[2 * q] = best; top2_out[2 * q + 1] = second; }
         }
@@ -317,11 +337,13 @@ int orc_build_ivf(int32_t k, int64_t d, const int64_t* cp, const int32_t* ccol, 
  * ------------------------------------------------------------------------ */
 int orc_multadds(int64_t n, const int64_t* rp, const int32_t* col, const int64_t* term_ptr,
                  const int32_t* split, const int32_t* cid, int icp, const uint8_t* lam_prev,
-                 const int32_t* a_prev, int mode, int64_t* per_row, int64_t* total) {
+                 const int32_t* a_prev, int mode, const uint8_t* branch, int64_t* per_row, int64_t* total) {
     int64_t sum = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : sum)
     for (int64_t i = 0; i < n; ++i) {
-        int use_icp = mode != 2 && icp && lam_prev && a_prev && lam_prev[a_prev[i]];
+        /* branch[i] != 0: the object compared moving centroids only (ICP or relaxed ICP) */
+        int use_icp = mode != 2 && icp && lam_prev && a_prev &&
+                      (branch ? branch[i] != 0 : lam_prev[a_prev[i]] != 0);
         int64_t c = 0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
             int32_t s = col[p];

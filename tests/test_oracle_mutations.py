@@ -51,6 +51,10 @@ MUTATIONS = {
         "        q0[s] = term_ptr[s];\n        q1[s] = term_ptr[s] + mf0[s];",
         "        q0[s] = term_ptr[s] + mf1[s];\n        q1[s] = term_ptr[s];",
         [lambda: pins.test_ivf_layout_and_roundtrip()]),
+    "relaxed_icp_condition_reversed": (
+        "acc[a_prev[i]] >= own_prev[i];",
+        "acc[a_prev[i]] <= own_prev[i];",
+        [lambda: pins.test_relaxed_icp_equals_unfiltered_every_iteration(3)]),
     "cbicp_counts_invariant": (
         "c += (lam_prev[cid[q]] == 0);",
         "c += (lam_prev[cid[q]] != 0);",

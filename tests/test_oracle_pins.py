@@ -183,6 +183,35 @@ def test_icp_filtered_equals_unfiltered_every_iteration(seed):
     assert sum(int(l.sum()) for l in t1.lam) > 0  # some clusters became invariant
 
 
+@pytest.mark.parametrize("seed", [3, 4])
+def test_relaxed_icp_equals_unfiltered_every_iteration(seed):
+    # Relaxed ICP (Section 2.1, after Bottesch et al.): an object whose own
+    # centroid moved but got no less similar skips the invariant centroids.
+    # Plain Lloyd's assignments (unfiltered, by definition) must not change,
+    # the relaxed branch must occur, and it may only lower the count.
+    c = synth.make_corpus(3000, 400, 20, 1.0, np.float64, seed=seed)
+    ids = synth.init_ids(3000, 40, seed)
+    t2 = oracle.lloyd(c, 40, ids, 25, icp=True, relaxed=True, keep_centroids=True)
+    t1 = oracle.lloyd(c, 40, ids, 25, icp=True)
+    t0 = oracle.lloyd(c, 40, ids, 25, icp=False)
+    assert t2.iters == t0.iters
+    for r in range(t2.iters):
+        assert np.array_equal(t2.assign[r], t0.assign[r])
+        assert np.array_equal(t2.own[r], t0.own[r])
+        assert t2.multadds[r] <= t1.multadds[r]
+        if r >= 1:
+            # exactly the objects whose own cluster moved and whose FP64
+            # similarity to it did not decrease take the relaxed branch
+            a_prev = t2.assign[r - 1]
+            moving_own = t2.lam[r - 1][a_prev] == 0
+            now = oracle.pair_sims(c, t2.centroids[r], np.arange(c.n), a_prev)
+            want = moving_own & (now >= t2.own[r - 1])
+            assert np.array_equal(t2.branch[r] == 2, want)
+            assert np.array_equal(t2.branch[r] == 1, ~moving_own)
+    assert sum(int((b == 2).sum()) for b in t2.branch) > 0
+    assert sum(t2.multadds) < sum(t1.multadds)
+
+
 def test_sivf_and_cbicp_counts_equal_and_not_above_ivf():
     c = synth.make_corpus(2000, 300, 15, 1.0, np.float64, seed=9)
     ids = synth.init_ids(2000, 30, 9)
