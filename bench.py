@@ -169,10 +169,10 @@ def run_lloyd_timed(ctx, X, k, ids, steps, warmup, posting):
         st["t_update_ms"] = up["t_update_ms"]
         stats.append(st)
         log("%s iter %d: M=%.3e walk %.1f ms assign %.1f ms update %.1f ms moved %d inv %d icp %d rescored %d/%d "
-            "full %d head rows %d"
+            "full %d head rows %d relaxed %d"
             % (posting, r, st["multadds"], st["t_walk_ms"], st["t_assign_ms"], st["t_update_ms"], st["moved"],
                st["n_invariant"], st["icp_objects"], st["rescored_objects"], st["rescored_candidates"],
-               st["full_rescored"], st["head_rows"]))
+               st["full_rescored"], st["head_rows"], st["relaxed_objects"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assign_a = L.a.clone()
@@ -238,8 +238,9 @@ def main():
     ap.add_argument("--skip-soft", action="store_true", help="skip the differentiation-form timing")
     ap.add_argument("--icp-head-moving", type=float, default=None,
                     help="ICP objects read head rows in tiles with at least this moving fraction (default: library's)")
-    ap.add_argument("--filter", default="sivf", choices=["sivf", "ivf", "cbicp"],
-                    help="ICP realisation: structured file (SIVF), none (IVF), per-posting test (IVF-CBICP)")
+    ap.add_argument("--filter", default="sivf", choices=["sivf", "ivf", "cbicp", "relaxed"],
+                    help="ICP realisation: structured file (SIVF), none (IVF), per-posting test (IVF-CBICP), "
+                         "SIVF with relaxed ICP")
     ap.add_argument("--workload", default="8m-f32", help="synthetic workload name (8m-f32, 8m-bf16-k20k, 1m-f32)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 copies of 1 GiB (counter calibration for the traffic figure)")
@@ -328,7 +329,8 @@ def main():
                    "n": corpus.n, "d": corpus.d, "k": k, "nnz": corpus.nnz, "k_tile": sizes["k_tile"],
                    "n_tiles": sizes["n_tiles"],
                    "filter": {"sivf": "SIVF (ICP via structured file)", "ivf": "IVF (no ICP)",
-                              "cbicp": "IVF-CBICP (ICP by per-posting flag test)"}[args.filter]},
+                              "cbicp": "IVF-CBICP (ICP by per-posting flag test)",
+                              "relaxed": "SIVF with relaxed ICP"}[args.filter]},
         "s_per_iter": s32["s_per_iter"],
         "iter1_multadds_per_s": s32["iter1_multadds_per_s"],
         "assign_s": s32["assign_s"], "update_s": s32["update_s"],

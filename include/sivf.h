@@ -68,8 +68,17 @@ typedef enum { SIVF_F32 = 0, SIVF_F64 = 1, SIVF_BF16 = 2 } sivf_dtype;
  *         invariant reads only the moving (front) part of each list (Alg. 4).
  *  IVF  : no filter; every object reads whole lists (Alg. 2).
  *  CBICP: ICP through a per-posting test of the centroid's flag over whole
- *         lists (Alg. 3); same result and same mult-add count as SIVF. */
-typedef enum { SIVF_MODE_SIVF = 0, SIVF_MODE_IVF = 1, SIVF_MODE_CBICP = 2 } sivf_filter_mode;
+ *         lists (Alg. 3); same result and same mult-add count as SIVF.
+ *  RELAXED: SIVF, and also an object whose own cluster moved but whose FP64
+ *         similarity to its own centroid did not decrease reads only the
+ *         moving parts (the relaxed ICP condition of Section 2.1; same
+ *         assignments as plain Lloyd).  Needs own64_inout in sivf_assign. */
+typedef enum {
+    SIVF_MODE_SIVF = 0,
+    SIVF_MODE_IVF = 1,
+    SIVF_MODE_CBICP = 2,
+    SIVF_MODE_RELAXED = 3
+} sivf_filter_mode;
 
 /* A sparse matrix in CSR form, all arrays on the device.
  * row_ptr: int64[n_rows + 1], row_ptr[0] = 0, non-decreasing, row_ptr[n_rows] = nnz.
@@ -133,6 +142,7 @@ typedef struct {
     float t_assign_ms;           /* whole assignment step (walk + re-score + flags) */
     float t_update_ms;           /* whole update step (means + structured file) */
     int64_t head_rows;           /* dense head rows the walk read (see head_density) */
+    int64_t relaxed_objects;     /* objects that took the relaxed ICP branch */
 } sivf_iter_stats;
 
 typedef struct sivf_ctx sivf_ctx;  /* device, stream, options, workspace, last error */
@@ -202,13 +212,19 @@ sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* ivf, int64_t* c_ptr, 
  *                          iter == 1); out the similarity of each object to its
  *                          new centroid (fast-pass value or FP64 re-score
  *                          rounded to FP32).
+ *  own64_inout f64[N]:     RELAXED mode only (else may be NULL): in the values
+ *                          this call wrote at r-1 (ignored when iter == 1);
+ *                          out the exact FP64 similarity of each object to its
+ *                          new centroid (the oracle's value, bitwise).
  *  lambda_out uint8[k]:    out lambda^[r] (1 iff the cluster's members are the
  *                          same at r-1 and r; all 0 when iter == 1).
  *  stats_host:             optional; non-NULL makes the call wait.
- * ICP branch: iter >= 2, filter mode SIVF/CBICP, and the file's flag of the
- * object's previous cluster is 1. */
+ * ICP branch: iter >= 2, filter mode SIVF/CBICP/RELAXED, and the file's flag
+ * of the object's previous cluster is 1.  Relaxed branch (RELAXED): iter >= 2,
+ * that flag is 0, and the object's FP64 similarity to its previous centroid
+ * now is >= own64_inout. */
 sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* ivf, int32_t iter,
-                        int32_t* assign_inout, float* own_sim_inout, uint8_t* lambda_out,
+                        int32_t* assign_inout, float* own_sim_inout, double* own64_inout, uint8_t* lambda_out,
                         sivf_iter_stats* stats_host);
 
 /* Update step r (Alg. 5): replace the file's centroids by mu^[r] computed from

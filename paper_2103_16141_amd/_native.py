@@ -11,7 +11,7 @@ SIVF_OK = 0
 STATUS = {0: "SIVF_OK", -1: "SIVF_E_INVALID", -2: "SIVF_E_SHAPE", -3: "SIVF_E_UNSORTED", -4: "SIVF_E_RANGE",
           -5: "SIVF_E_NONFINITE", -6: "SIVF_E_NOMEM", -7: "SIVF_E_HIP", -8: "SIVF_E_UNSUPPORTED"}
 SIVF_F32, SIVF_F64, SIVF_BF16 = 0, 1, 2
-SIVF_MODE_SIVF, SIVF_MODE_IVF, SIVF_MODE_CBICP = 0, 1, 2
+SIVF_MODE_SIVF, SIVF_MODE_IVF, SIVF_MODE_CBICP, SIVF_MODE_RELAXED = 0, 1, 2, 3
 
 
 class sivf_csr(ctypes.Structure):
@@ -32,7 +32,8 @@ class sivf_iter_stats(ctypes.Structure):
                 ("moved", ctypes.c_int64), ("icp_objects", ctypes.c_int64), ("rescored_objects", ctypes.c_int64),
                 ("rescored_candidates", ctypes.c_int64), ("full_rescored", ctypes.c_int64),
                 ("objective_fast", ctypes.c_double), ("t_walk_ms", ctypes.c_float),
-                ("t_assign_ms", ctypes.c_float), ("t_update_ms", ctypes.c_float), ("head_rows", ctypes.c_int64)]
+                ("t_assign_ms", ctypes.c_float), ("t_update_ms", ctypes.c_float), ("head_rows", ctypes.c_int64),
+                ("relaxed_objects", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -71,7 +72,7 @@ def load(path: str = LIB_PATH):
         "sivf_ivf_free": ([vp, vp], st),
         "sivf_ivf_sizes": ([vp, vp, P(i32), P(i64), P(i64), P(i32), P(i32)], st),
         "sivf_ivf_export": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], st),
-        "sivf_assign": ([vp, csr_p, vp, i32, vp, vp, vp, stats_p], st),
+        "sivf_assign": ([vp, csr_p, vp, i32, vp, vp, vp, vp, stats_p], st),
         "sivf_update": ([vp, csr_p, vp, vp, vp, stats_p], st),
         "sivf_run_lloyd": ([vp, csr_p, i32, vp, i32, vp, vp, P(vp), stats_p, P(i32)], st),
         "sivf_soft_assign_fwd": ([vp, csr_p, vp, i32, f32, vp, P(ctypes.c_double)], st),

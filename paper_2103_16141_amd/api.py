@@ -118,7 +118,8 @@ class Context:
         opt = N.sivf_options()
         lib.sivf_default_options(ctypes.byref(opt))
         opt.posting_dtype = {"fp32": N.SIVF_F32, "bf16": N.SIVF_BF16}[posting_dtype]
-        opt.filter_mode = {"sivf": N.SIVF_MODE_SIVF, "ivf": N.SIVF_MODE_IVF, "cbicp": N.SIVF_MODE_CBICP}[filter_mode]
+        opt.filter_mode = {"sivf": N.SIVF_MODE_SIVF, "ivf": N.SIVF_MODE_IVF, "cbicp": N.SIVF_MODE_CBICP,
+                           "relaxed": N.SIVF_MODE_RELAXED}[filter_mode]
         opt.k_tile = int(k_tile)
         opt.certify = 1 if certify else 0
         opt.workspace_cap_bytes = int(workspace_cap_bytes)
@@ -173,11 +174,11 @@ class Context:
         self._chk(N.load().sivf_build_centroid_ivf(self.handle, ctypes.byref(s), _ptr(lam), ctypes.byref(h)))
         return Ivf(self, h)
 
-    def assign(self, X: DeviceCsr, ivf: Ivf, it: int, a, own, lam_out, stats=True):
+    def assign(self, X: DeviceCsr, ivf: Ivf, it: int, a, own, lam_out, stats=True, own64=None):
         s = X.struct()
         st = N.sivf_iter_stats()
         self._chk(N.load().sivf_assign(self.handle, ctypes.byref(s), ivf.handle, int(it), _ptr(a), _ptr(own),
-                                       _ptr(lam_out), ctypes.byref(st) if stats else None))
+                                       _ptr(own64), _ptr(lam_out), ctypes.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def update(self, X: DeviceCsr, a, lam, ivf: Ivf, stats=True):
@@ -228,11 +229,14 @@ class Lloyd:
         self.a = torch.zeros(X.n_rows, dtype=torch.int32, device=dev)
         self.own = torch.zeros(X.n_rows, dtype=torch.float32, device=dev)
         self.lam = torch.zeros(k, dtype=torch.uint8, device=dev)
+        # exact own similarities, the state of the relaxed ICP filter
+        relaxed = ctx.opt.filter_mode == N.SIVF_MODE_RELAXED
+        self.own64 = torch.zeros(X.n_rows, dtype=torch.float64, device=dev) if relaxed else None
         self.r = 0
 
     def assign(self):
         self.r += 1
-        return self.ctx.assign(self.X, self.ivf, self.r, self.a, self.own, self.lam)
+        return self.ctx.assign(self.X, self.ivf, self.r, self.a, self.own, self.lam, own64=self.own64)
 
     def update(self):
         return self.ctx.update(self.X, self.a, self.lam, self.ivf)

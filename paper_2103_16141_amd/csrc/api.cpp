@@ -371,7 +371,7 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     sivf_default_options(&o);
     if (opt) o = *opt;
     if (o.posting_dtype != SIVF_F32 && o.posting_dtype != SIVF_BF16) return SIVF_E_INVALID;
-    if (o.filter_mode < 0 || o.filter_mode > 2) return SIVF_E_INVALID;
+    if (o.filter_mode < 0 || o.filter_mode > 3) return SIVF_E_INVALID;
     if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
     if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
     if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
@@ -551,10 +551,12 @@ sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* f, int64_t* c_ptr, in
 }
 
 sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
-                        float* own_sim_inout, uint8_t* lambda_out, sivf_iter_stats* stats_host) {
+                        float* own_sim_inout, double* own64_inout, uint8_t* lambda_out, sivf_iter_stats* stats_host) {
     if (!ctx) return SIVF_E_INVALID;
     DevGuard g(ctx->device);
     if (!f || !assign_inout || !own_sim_inout || !lambda_out) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    const int relaxed = ctx->opt.filter_mode == SIVF_MODE_RELAXED;
+    if (relaxed && !own64_inout) return fail(ctx, SIVF_E_INVALID, "the RELAXED filter needs own64_inout");
     if (iter < 1) return fail(ctx, SIVF_E_INVALID, "iter must be >= 1");
     Csr Xc;
     STCHK(validate(ctx, X, &Xc, false));
@@ -626,6 +628,18 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
         STCHK(ws(ctx, "st_cj", m * kCandCap, &A.st_cj));
         STCHK(ws(ctx, "st_cr", m * kCandCap, &A.st_cr));
     }
+    A.st = f->cur;
+    A.relaxed = relaxed;
+    A.own64_prev = own64_inout;
+    A.own64_cur = nullptr;
+    A.st_rel = nullptr;
+    int32_t* own64_queue = nullptr;
+    if (relaxed) {
+        const int64_t m = std::max<int64_t>(n, 1);
+        STCHK(ws(ctx, "own64_cur", m, &A.own64_cur));
+        STCHK(ws(ctx, "own64_queue", m, &own64_queue));
+        if (launches > 1) STCHK(ws(ctx, "st_rel", m, &A.st_rel));
+    }
     A.head = f->H > 0 ? f->head : nullptr;
     A.icp_head = f->icp_head;
     A.hval = f->hval;
@@ -646,6 +660,7 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     if (n > 0) {
         HIPCHK(ctx, rescore_candidates(A, f->cur, (int64_t)ctx->n_cu * 16, s));
         HIPCHK(ctx, rescore_full(A, f->v64, f->cur, (int64_t)ctx->n_cu * 4, s));
+        if (relaxed) HIPCHK(ctx, own64_update(A, own64_inout, own64_queue, (int64_t)ctx->n_cu * 16, s));
         HIPCHK(ctx, finalize_assign(n, iter, a_new, own_new, assign_inout, own_sim_inout, changed, counters,
                                     obj_partial, nfin, s));
     }
@@ -668,6 +683,7 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
         stats_host->n_invariant = (int32_t)c[6];
         stats_host->objective_fast = o;
         stats_host->head_rows = f->H;
+        stats_host->relaxed_objects = (int64_t)c[7];
         float t = 0.0f;
         HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
         stats_host->t_walk_ms = t;
@@ -749,10 +765,13 @@ sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const in
     if (!a) st = ws(ctx, "lloyd_a", Xc.n, &a);
     if (st == SIVF_OK && !own) st = ws(ctx, "lloyd_own", Xc.n, &own);
     if (st == SIVF_OK) st = ws(ctx, "lloyd_lam", k, &lam);
+    double* own64 = nullptr;   // exact own similarities (relaxed ICP state)
+    if (st == SIVF_OK && ctx->opt.filter_mode == SIVF_MODE_RELAXED)
+        st = ws(ctx, "lloyd_own64", std::max<int64_t>(Xc.n, 1), &own64);
     int32_t done = 0;
     for (int32_t r = 1; st == SIVF_OK && r <= max_iter; ++r) {
         sivf_iter_stats stt{};
-        st = sivf_assign(ctx, X, f, r, a, own, lam, &stt);
+        st = sivf_assign(ctx, X, f, r, a, own, own64, lam, &stt);
         if (st != SIVF_OK) break;
         done = r;
         if (per_iter_host) per_iter_host[r - 1] = stt;

@@ -70,6 +70,7 @@ struct WalkArgs {
     int32_t* fobj;          // full re-score queue: object ids
     unsigned long long* counters;  // [0] multadds [1] queue len [2] full len [3] icp objects
                                    // [4] re-scored candidates [5] moved [6] invariant
+                                   // [7] relaxed-ICP objects [9] own64 queue length
                                    // [16 + launch] walk work counters
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)
@@ -78,6 +79,12 @@ struct WalkArgs {
     const void* hval;       // [H * kpad] values in the posting dtype
     int64_t kpad;           // row length: T * kt
     int64_t hbytes;         // bytes of hval (< 2^32)
+    // relaxed ICP (filter mode RELAXED)
+    Store st;                  // the current centroids (FP64 CSR) for exact similarities
+    int relaxed;
+    const double* own64_prev;  // [n] exact rho to the previous centroid under the previous centroids
+    double* own64_cur;         // [n] exact rho to the previous centroid under the current centroids
+    uint8_t* st_rel;           // [n] relaxed branch taken (kept between tile launches)
     // per-object running state between launches over successive tile ranges
     double* st_theta;       // [n] largest lower bound so far
     double* st_best;        // [n] best lower bound (diagnostic argmax)
@@ -189,6 +196,8 @@ hipError_t walk_fast(const WalkArgs& a, int pdt_bf16, int grid_waves, int tb, in
                      hipStream_t s);
 int walk_blocks_per_cu(int kt, int pdt_bf16, int cbicp);
 hipError_t rescore_candidates(const WalkArgs& a, const Store st, int64_t grid_waves, hipStream_t s);
+// exact FP64 similarity of every object to its new centroid (relaxed ICP state)
+hipError_t own64_update(const WalkArgs& a, double* own64, int32_t* queue, int64_t grid_waves, hipStream_t s);
 hipError_t rescore_full(const WalkArgs& a, const double* v64, const Store st, int64_t grid, hipStream_t s);
 hipError_t finalize_assign(int64_t n, int iter, const int32_t* a_new, const float* own_new, int32_t* a_io,
                            float* own_io, uint8_t* changed, unsigned long long* counters,

@@ -229,6 +229,48 @@ __device__ inline void dense_accumulate(float* sim, const DBatch& b, int ub, int
 }
 
 // ---------------------------------------------------------------------------
+// FP64 re-score in the reference order
+// ---------------------------------------------------------------------------
+// rho_ij for one (object, centroid): lanes take the object's terms 64 at a
+// time, look each up in the centroid's sorted term list (binary search), and
+// the wave then folds the products sequentially in ascending term order.
+__device__ double exact_rho(const WalkArgs& A, const Store& st, int64_t r0, int n, int32_t j) {
+    const int lane = threadIdx.x & 63;
+    const int64_t cs = st.start[j];
+    const int64_t cm = st.nnz[j];
+    double acc = 0.0;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int h = c0 + lane;
+        bool present = false;
+        double prod = 0.0;
+        if (h < n) {
+            const int32_t t = A.col[r0 + h];
+            int64_t lo = 0, len = cm;
+            while (len > 0) {
+                const int64_t half = len >> 1;
+                if (st.term[cs + lo + half] < t) {
+                    lo += half + 1;
+                    len -= half + 1;
+                } else {
+                    len = half;
+                }
+            }
+            if (lo < cm && st.term[cs + lo] == t) {
+                present = true;
+                prod = load_xval64(A.xval, A.x_f64, r0 + h) * st.val[cs + lo];
+            }
+        }
+        unsigned long long m = ballot(present);
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            acc = acc + bcast_f64(prod, l);
+            m &= m - 1;
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
 // fast pass
 // ---------------------------------------------------------------------------
 template <bool BF16, bool CB>
@@ -247,7 +289,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
-    unsigned long long macc = 0, icp_cnt = 0;
+    unsigned long long macc = 0, icp_cnt = 0, rel_cnt = 0;
     constexpr int kGrab = 8;
     for (int64_t g0 = wave_grab(work, kGrab); g0 < A.n; g0 = wave_grab(work, kGrab)) {
         const int64_t gend = min(g0 + kGrab, A.n);
@@ -300,7 +342,24 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 ccount = 1;
             }
             bool overflow = ccount > kCandCap;
-            const bool front_only = icp && !CB;
+            // relaxed ICP: own cluster moved, but the exact similarity to the
+            // own centroid did not decrease -> moving centroids only
+            bool rel = false;
+            if (A.relaxed && A.icp_on && !icp) {
+                if (tb == 0) {
+                    const double rn = exact_rho(A, A.st, r0, n, a_old);
+                    rel = rn >= A.own64_prev[i];
+                    if (lane == 0) {
+                        A.own64_cur[i] = rn;
+                        if (te < A.T) A.st_rel[i] = rel ? 1 : 0;
+                    }
+                    rel_cnt += rel ? 1 : 0;
+                } else {
+                    rel = A.st_rel[i] != 0;
+                }
+            }
+            const bool filt = icp || rel;   // compare moving centroids only
+            const bool front_only = filt && !CB;
             const bool test_flag = icp && CB;
 
             // Stage the object's first kTermCap terms and values in LDS once
@@ -361,7 +420,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                 // ascending term order, 512 centroids per batch, next batch in
                 // flight while the current one is accumulated
                 int hrow = -1;
-                const bool use_head = A.head && (!icp || (!CB && A.icp_head[tile]));
+                const bool use_head = A.head && (!filt || (!CB && A.icp_head[tile]));
                 if (use_head && h < n) hrow = h < kTermCap ? th[h] : A.head[A.col[r0 + h]];
                 unsigned long long dl = ballot(hrow >= 0);
                 if (dl) {
@@ -470,7 +529,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                         for (int jj = lane; jj < width; jj += 64) {
                             const int32_t j = base + jj;
                             const float r = sim[jj];
-                            if ((!icp || A.lam[j] == 0) && r > rmax) {
+                            if ((!filt || A.lam[j] == 0) && r > rmax) {
                                 rmax = r;
                                 rj = j;
                             }
@@ -484,7 +543,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                     } else {
                         for (int jj = lane; jj < width; jj += 64) {
                             const int32_t j = base + jj;
-                            const bool elig = !icp || A.lam[j] == 0;
+                            const bool elig = !filt || A.lam[j] == 0;
                             if (elig) {
                                 const double r = (double)sim[jj];
                                 const double lo = r - bound_of(A, bd, r, j);
@@ -539,7 +598,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
                             const int32_t j = base + jj;
                             r32 = sim[jj];
                             sim[jj] = 0.0f;
-                            if (r32 >= rlow && (!icp || A.lam[j] == 0)) {
+                            if (r32 >= rlow && (!filt || A.lam[j] == 0)) {
                                 const double r = (double)r32;
                                 take = r + bound_of(A, bd, r, j) >= theta;
                             }
@@ -610,6 +669,7 @@ __global__ __launch_bounds__(256) void k_walk_fast(WalkArgs A, unsigned long lon
     if (lane == 0) {
         atomicAdd(&A.counters[0], macc);
         atomicAdd(&A.counters[3], icp_cnt);
+        if (rel_cnt) atomicAdd(&A.counters[7], rel_cnt);
     }
 }
 
@@ -646,48 +706,6 @@ int walk_blocks_per_cu(int kt, int pdt_bf16, int cbicp) {
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel(pdt_bf16, cbicp), 64 * kWalkWaves, lds);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
-}
-
-// ---------------------------------------------------------------------------
-// FP64 re-score in the reference order
-// ---------------------------------------------------------------------------
-// rho_ij for one (object, centroid): lanes take the object's terms 64 at a
-// time, look each up in the centroid's sorted term list (binary search), and
-// the wave then folds the products sequentially in ascending term order.
-__device__ double exact_rho(const WalkArgs& A, const Store& st, int64_t r0, int n, int32_t j) {
-    const int lane = threadIdx.x & 63;
-    const int64_t cs = st.start[j];
-    const int64_t cm = st.nnz[j];
-    double acc = 0.0;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-        const int h = c0 + lane;
-        bool present = false;
-        double prod = 0.0;
-        if (h < n) {
-            const int32_t t = A.col[r0 + h];
-            int64_t lo = 0, len = cm;
-            while (len > 0) {
-                const int64_t half = len >> 1;
-                if (st.term[cs + lo + half] < t) {
-                    lo += half + 1;
-                    len -= half + 1;
-                } else {
-                    len = half;
-                }
-            }
-            if (lo < cm && st.term[cs + lo] == t) {
-                present = true;
-                prod = load_xval64(A.xval, A.x_f64, r0 + h) * st.val[cs + lo];
-            }
-        }
-        unsigned long long m = ballot(present);
-        while (m) {
-            const int l = __ffsll((long long)m) - 1;
-            acc = acc + bcast_f64(prod, l);
-            m &= m - 1;
-        }
-    }
-    return acc;
 }
 
 __global__ __launch_bounds__(256) void k_rescore_cand(WalkArgs A, Store st) {
@@ -892,6 +910,53 @@ hipError_t finalize_lambda(int32_t k, int iter, const uint8_t* changed, uint8_t*
                            const double* obj_partial, int nblk, double* obj_out, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize_lambda, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, k, iter, changed,
                        lam_out, counters, obj_partial, nblk, obj_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact own similarities for the next relaxed ICP decision: the FP64 rho of
+// each object to its new centroid.  An object that kept its centroid reuses
+// the value from this step (moving centroid: computed by the walk) or from
+// the previous one (invariant centroid: unchanged); the others are queued and
+// re-scored with exact_rho.
+// ---------------------------------------------------------------------------
+__global__ void k_own64_known(WalkArgs A, double* __restrict__ own64, int32_t* __restrict__ queue) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int32_t an = A.a_new[i];
+    bool known = false;
+    if (A.icp_on && A.a_prev[i] == an) {
+        known = true;
+        if (!A.lam[an]) own64[i] = A.own64_cur[i];   // else: unchanged centroid, value stays
+    }
+    if (!known) {
+        const unsigned long long slot = atomicAdd(&A.counters[9], 1ull);
+        queue[slot] = (int32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_own64_exact(WalkArgs A, double* __restrict__ own64,
+                                                      const int32_t* __restrict__ queue) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nq = (int64_t)A.counters[9];
+    for (int64_t q = wave; q < nq; q += nw) {
+        const int32_t i = queue[q];
+        const int64_t r0 = A.rp[i];
+        const double r = exact_rho(A, A.st, r0, (int)(A.rp[i + 1] - r0), A.a_new[i]);
+        if (lane == 0) own64[i] = r;
+    }
+}
+
+hipError_t own64_update(const WalkArgs& a, double* own64, int32_t* queue, int64_t grid_waves, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_own64_known, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, own64, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t blocks = (grid_waves + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_own64_exact, dim3((unsigned)blocks), dim3(256), 0, s, a, own64, queue);
     return hipGetLastError();
 }
 

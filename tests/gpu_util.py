@@ -31,7 +31,7 @@ def lloyd_parity(ctx, X, corpus, k, ids, max_iter, icp=True, mode="sivf", check_
                  check_ivf_every=1):
     """Run GPU and oracle Lloyd side by side; assert identical trajectories."""
     from paper_2103_16141_amd.api import Lloyd
-    tr = oracle.lloyd(corpus, k, ids, max_iter, icp=icp, keep_centroids=True)
+    tr = oracle.lloyd(corpus, k, ids, max_iter, icp=icp, keep_centroids=True, relaxed=(mode == "relaxed"))
     L = Lloyd(ctx, X, k, ids)
     gpu_stats = []
     for r in range(1, tr.iters + 1):

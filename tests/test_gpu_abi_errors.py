@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import log
+from tests.gpu_util import device, log
 from tests.util import corpus_from_rows
 
 pytestmark = pytest.mark.gpu
@@ -103,7 +103,7 @@ def test_null_pointers_and_bad_options():
     assert lib.sivf_validate_csr(ctx.handle, None) == -1
     assert b"NULL" in lib.sivf_last_error(ctx.handle)
     st = N.sivf_iter_stats()
-    assert lib.sivf_assign(ctx.handle, None, None, 1, None, None, None, ctypes.byref(st)) == -1
+    assert lib.sivf_assign(ctx.handle, None, None, 1, None, None, None, None, ctypes.byref(st)) == -1
     assert lib.sivf_destroy(None) == 0 and lib.sivf_ivf_free(ctx.handle, None) == 0
 
 
@@ -115,6 +115,23 @@ def test_workspace_cap_reports_nomem():
     assert _status(lambda: ctx.init_centroids(X, 5, [0, 1, 2, 3, 4])) == "SIVF_E_NOMEM"
     ctx2 = _ctx(workspace_cap_bytes=1 << 30)
     a, own, ivf, stats = ctx2.run_lloyd(X, 5, [0, 1, 2, 3, 4], 5)
+    assert len(stats) >= 1
+
+
+def test_relaxed_filter_needs_own64():
+    log("abi errors: relaxed filter without own64")
+    ctx = _ctx(filter_mode="relaxed")
+    c = _good()
+    X = _X(c)
+    ivf = ctx.init_centroids(X, 5, [0, 1, 2, 3, 4])
+    a = torch.zeros(c.n, dtype=torch.int32, device=device())
+    own = torch.zeros(c.n, dtype=torch.float32, device=device())
+    lam = torch.zeros(5, dtype=torch.uint8, device=device())
+    assert _status(lambda: ctx.assign(X, ivf, 1, a, own, lam)) == "SIVF_E_INVALID"
+    # with the state it runs, and run_lloyd keeps the state itself
+    own64 = torch.zeros(c.n, dtype=torch.float64, device=device())
+    ctx.assign(X, ivf, 1, a, own, lam, own64=own64)
+    a2, own2, ivf2, stats = ctx.run_lloyd(X, 5, [0, 1, 2, 3, 4], 6)
     assert len(stats) >= 1
 
 

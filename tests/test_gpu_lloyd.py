@@ -33,7 +33,7 @@ def test_small_f64_trajectory(k_tile, posting):
     assert tr.iters >= 5
 
 
-@pytest.mark.parametrize("mode", ["sivf", "ivf", "cbicp"])
+@pytest.mark.parametrize("mode", ["sivf", "ivf", "cbicp", "relaxed"])
 def test_filter_modes_same_assignments(mode):
     log("filter mode %s" % mode)
     c = synth.make_corpus(2500, 700, 20, 1.0, np.float64, seed=102)
@@ -185,3 +185,18 @@ def test_icp_objects_reading_head_rows(posting):
         icp_seen = max(icp_seen, sum(s["icp_objects"] for s in st))
         ctx.close()
     assert icp_seen > 0
+
+
+@pytest.mark.parametrize("posting,tiles_per_launch", [("fp32", 0), ("bf16", 0), ("fp32", 64)])
+def test_relaxed_icp_trajectory(posting, tiles_per_launch):
+    # Relaxed ICP (Section 2.1): objects whose own centroid moved but got no
+    # less similar (exact FP64) skip invariant centroids.  Assignments, flags,
+    # mult-add counts and centroids match the oracle's relaxed run step by
+    # step; the branch is taken; one launch per tile or all tiles at once.
+    log("relaxed ICP posting=%s tiles_per_launch=%d" % (posting, tiles_per_launch))
+    c = synth.make_corpus(20000, 3000, 40, 1.1, np.float32, seed=112)
+    ids = synth.init_ids(20000, 300, 18)
+    ctx = _ctx(k_tile=128, posting_dtype=posting, filter_mode="relaxed", tiles_per_launch=tiles_per_launch)
+    tr, st = lloyd_parity(ctx, _X(c), c, 300, ids, 12, mode="relaxed", check_ivf_every=4)
+    assert sum(s["relaxed_objects"] for s in st) > 0
+    assert [s["relaxed_objects"] for s in st] == [int((b == 2).sum()) for b in tr.branch[:len(st)]]
