@@ -1,20 +1,23 @@
 """Full-size checks in the launch configuration bench.py times.
 
 N = 8M objects, D = 140k, k = 10k, automatic tiles (the headline workload):
-  * iteration 1 on sampled objects against the oracle (its inputs are the
-    seeded corpus and the seeded initial centroids only);
-  * properties that hold at any size for later steps, checked on samples with
-    dense FP64 numpy (not the oracle): each sampled centroid after update 1 is
-    the normalised mean of the objects the GPU assigned to it; each sampled
-    object's iteration-2 assignment maximises the FP64 similarity against the
-    GPU's centroids; SIVF (ICP) and IVF (no filter) runs give identical
-    assignments and the SIVF count never exceeds the IVF count.
+  * iterations 1-4 one step at a time against the oracle: from the GPU's
+    previous assignment the oracle's update must give the GPU's centroids bit
+    for bit, and sampled objects' assignments against them must match
+    exactly; flags, moved counts and the exact mult-add count over all
+    objects; the structured file after update 2;
+  * sampled centroids after update 1 against dense FP64 numpy means (not the
+    oracle);
+  * SIVF, IVF, relaxed ICP and BF16 postings give identical assignments over
+    3 iterations; the SIVF count never exceeds the IVF count, the relaxed
+    count never exceeds the SIVF count, BF16 counts equal FP32 counts.
 Soft form at its full shape (N = 262,144, D = 100k, k = 4,096): sampled rows'
 lse and dX and sampled columns of dC against the oracle; the dC column-sum
 identity over all columns.
 NYT-shaped corpus (N = 1,285,944, D = 495,714, ~226 nonzeros per row, k =
-10k): iteration 1 on sampled objects against the oracle, iteration 2 against
-dense FP64 numpy on samples.
+10k): iteration 1 on sampled objects against the oracle; update 1 bit for bit
+against the oracle's update of the GPU's assignment; iteration 2 on sampled
+objects, flags and the exact mult-add count.
 """
 import math
 
@@ -39,79 +42,102 @@ def headline():
     return corpus, ids, w, X
 
 
-def _rows_dense(corpus, rows, term_index):
-    out = np.zeros((len(rows), len(term_index)), dtype=np.float64)
-    for r, i in enumerate(rows):
-        b, e = corpus.row_ptr[i], corpus.row_ptr[i + 1]
-        out[r, [term_index[t] for t in corpus.col[b:e]]] = corpus.val[b:e]
-    return out
+def _export_centroids(ivf):
+    ex = ivf.export()
+    out = {key: ex[key].cpu().numpy() for key in ("c_ptr", "c_col", "c_val", "lam", "term_ptr", "split")}
+    return ex, out
 
 
-def test_headline_sampled_parity_and_properties(headline):
+def test_headline_one_step_parity(headline):
+    """Iterations 1-4 at full size, each checked against the oracle one step at
+    a time: the oracle updates from the GPU's previous assignment, so its
+    centroids must equal the GPU's bit for bit; sampled objects' assignments
+    against them must match exactly; the invariance flags and the exact
+    mult-add count are compared over all objects."""
     from paper_2103_16141_amd.api import Context, Lloyd
     corpus, ids, w, X = headline
     k = w["k"]
     ctx = Context(0)
     L = Lloyd(ctx, X, k, ids)
-    log("iteration 1 on the GPU")
-    st1 = L.assign()
-    a1 = L.a.cpu().numpy()
     rng = np.random.default_rng(1)
-    sample = np.sort(rng.choice(corpus.n, 1500, replace=False))
-    log("oracle on %d sampled objects" % len(sample))
-    ref, _, _ = oracle.assign(corpus, oracle.init_centroids(corpus, ids), rows=sample)
-    assert np.array_equal(a1[sample], ref)
-    assert st1["moved"] == corpus.n
-
-    log("update 1 and export")
-    L.update()
-    ex = L.ivf.export()
-    cptr = ex["c_ptr"].cpu().numpy()
-    ccol = ex["c_col"].cpu().numpy()
-    cval = ex["c_val"].cpu().numpy()
-    sizes = np.bincount(a1, minlength=k)
-    for j in rng.choice(np.nonzero(sizes > 0)[0], 12, replace=False):
-        mem = np.nonzero(a1 == j)[0]
-        idx = np.concatenate([np.arange(corpus.row_ptr[i], corpus.row_ptr[i + 1]) for i in mem])
-        w_ = np.zeros(corpus.d)
-        np.add.at(w_, corpus.col[idx], corpus.val[idx].astype(np.float64))
-        u = w_ / np.linalg.norm(w_)
-        got = np.zeros(corpus.d)
-        got[ccol[cptr[j]:cptr[j + 1]]] = cval[cptr[j]:cptr[j + 1]]
-        assert np.array_equal(np.nonzero(got)[0], np.nonzero(u)[0])
-        np.testing.assert_allclose(got, u, rtol=1e-12, atol=1e-300)
-
-    log("iteration 2 on the GPU")
-    L.assign()
-    a2 = L.a.cpu().numpy()
-    objs = np.sort(rng.choice(corpus.n, 200, replace=False))
-    terms = np.unique(np.concatenate([corpus.col[corpus.row_ptr[i]:corpus.row_ptr[i + 1]] for i in objs]))
-    tix = {int(t): r for r, t in enumerate(terms)}
-    Xs = _rows_dense(corpus, objs, tix)
-    M = np.zeros((len(terms), k))
-    rows_of = np.repeat(np.arange(k), np.diff(cptr))
-    keep = np.isin(ccol, terms)
-    M[np.searchsorted(terms, ccol[keep]), rows_of[keep]] = cval[keep]
-    rho = Xs @ M
-    best = rho.max(1)
-    got = rho[np.arange(len(objs)), a2[objs]]
-    assert np.all(got >= best - 1e-12 * np.maximum(1.0, np.abs(best)))
-    del M, rho
+    cents = oracle.init_centroids(corpus, ids)
+    a_prev = lam_prev = None
+    for r in range(1, 5):
+        log("iteration %d on the GPU" % r)
+        st = L.assign()
+        a = L.a.cpu().numpy()
+        own = L.own.cpu().numpy().astype(np.float64)
+        lam = L.lam.cpu().numpy()
+        sample = np.sort(rng.choice(corpus.n, 1500, replace=False))
+        log("oracle on %d sampled objects" % len(sample))
+        ref, ref_own, _ = oracle.assign(corpus, cents, rows=sample)
+        bad = np.nonzero(a[sample] != ref)[0]
+        assert len(bad) == 0, "iteration %d: sampled objects %s differ" % (r, sample[bad][:5])
+        rel = np.abs(own[sample] - ref_own) / np.maximum(np.abs(ref_own), 1e-30)
+        assert rel.max() < 1e-5, "iteration %d: own similarity off by %.3g" % (r, rel.max())
+        lam_ref, moved = oracle.mark_invariant(a_prev, a, k, first=(r == 1))
+        assert np.array_equal(lam, lam_ref), "iteration %d: flags differ" % r
+        assert st["moved"] == moved
+        log("oracle mult-add count over all objects")
+        m_ref = oracle.multadds(corpus, oracle.build_ivf(cents, lam_prev), icp=(r >= 2), lam_prev=lam_prev,
+                                a_prev=a_prev)
+        assert st["multadds"] == m_ref, "iteration %d: multadds %d vs %d" % (r, st["multadds"], m_ref)
+        if r >= 3:      # flags after iteration 1 are all zero, so ICP starts at iteration 3
+            assert st["icp_objects"] > 0
+        log("update %d: GPU and oracle" % r)
+        L.update()
+        cents, _ = oracle.update(corpus, a, cents)
+        ex, got = _export_centroids(L.ivf)
+        assert np.array_equal(got["c_ptr"], cents.ptr), "update %d: centroid sizes differ" % r
+        assert np.array_equal(got["c_col"], cents.col), "update %d: centroid supports differ" % r
+        assert np.array_equal(got["c_val"], cents.val), "update %d: centroid values differ" % r
+        assert np.array_equal(got["lam"], lam)
+        if r == 2:
+            log("structured file against the oracle's")
+            ivf_ref = oracle.build_ivf(cents, lam)
+            assert np.array_equal(got["term_ptr"], ivf_ref.term_ptr)
+            assert np.array_equal(got["split"], ivf_ref.split)
+            assert np.array_equal(ex["p_cid"].cpu().numpy(), ivf_ref.cid)
+            assert np.array_equal(ex["p_val"].cpu().numpy(), ivf_ref.val)
+            del ivf_ref
+        if r == 1:
+            # independent of the oracle: sampled centroids are the normalised
+            # means (dense FP64 numpy) of the objects the GPU assigned to them
+            sizes = np.bincount(a, minlength=k)
+            cptr, ccol, cval = got["c_ptr"], got["c_col"], got["c_val"]
+            for j in rng.choice(np.nonzero(sizes > 0)[0], 12, replace=False):
+                mem = np.nonzero(a == j)[0]
+                idx = np.concatenate([np.arange(corpus.row_ptr[i], corpus.row_ptr[i + 1]) for i in mem])
+                w_ = np.zeros(corpus.d)
+                np.add.at(w_, corpus.col[idx], corpus.val[idx].astype(np.float64))
+                u = w_ / np.linalg.norm(w_)
+                dense = np.zeros(corpus.d)
+                dense[ccol[cptr[j]:cptr[j + 1]]] = cval[cptr[j]:cptr[j + 1]]
+                assert np.array_equal(np.nonzero(dense)[0], np.nonzero(u)[0])
+                np.testing.assert_allclose(dense, u, rtol=1e-12, atol=1e-300)
+        del ex, got
+        a_prev, lam_prev = a, lam
+    ctx.close()
 
 
 def test_headline_filter_modes_agree(headline):
     from paper_2103_16141_amd.api import Context
     corpus, ids, w, X = headline
     res = {}
-    for mode in ("sivf", "ivf"):
-        log("3 iterations, filter %s" % mode)
-        ctx = Context(0, filter_mode=mode)
+    for mode, posting in (("sivf", "fp32"), ("ivf", "fp32"), ("relaxed", "fp32"), ("sivf", "bf16")):
+        log("3 iterations, filter %s, %s postings" % (mode, posting))
+        ctx = Context(0, filter_mode=mode, posting_dtype=posting)
         a, own, ivf, stats = ctx.run_lloyd(X, w["k"], ids, 3, keep_centroids=False)
-        res[mode] = (a.cpu().numpy(), [s["multadds"] for s in stats], [s["icp_objects"] for s in stats])
+        res[mode, posting] = (a.cpu().numpy(), [s["multadds"] for s in stats], [s["icp_objects"] for s in stats])
         ctx.close()
-    assert np.array_equal(res["sivf"][0], res["ivf"][0])
-    assert all(s <= i for s, i in zip(res["sivf"][1], res["ivf"][1]))
-    assert res["sivf"][2][2] > 0 and res["ivf"][2][2] == 0
+    base = res["sivf", "fp32"]
+    for key, (a, m, icp) in res.items():
+        assert np.array_equal(a, base[0]), key
+    assert res["sivf", "bf16"][1] == base[1]
+    assert all(s <= i for s, i in zip(base[1], res["ivf", "fp32"][1]))
+    assert all(r <= s for r, s in zip(res["relaxed", "fp32"][1], base[1]))
+    assert base[2][2] > 0 and res["ivf", "fp32"][2][2] == 0
+    assert res["relaxed", "fp32"][2][2] >= base[2][2]
 
 
 def test_soft_fullsize_sampled():
@@ -170,21 +196,21 @@ def test_nyt_shape_sampled():
     sample = np.sort(rng.choice(corpus.n, 600, replace=False))
     ref, _, _ = oracle.assign(corpus, oracle.init_centroids(corpus, ids), rows=sample)
     assert np.array_equal(a1[sample], ref)
-    log("update 1, iteration 2")
+    log("update 1 against the oracle, iteration 2")
     L.update()
-    ex = L.ivf.export()
-    L.assign()
+    cents, _ = oracle.update(corpus, a1, oracle.init_centroids(corpus, ids))
+    ex, got = _export_centroids(L.ivf)
+    assert np.array_equal(got["c_ptr"], cents.ptr)
+    assert np.array_equal(got["c_col"], cents.col)
+    assert np.array_equal(got["c_val"], cents.val)
+    del ex, got
+    st = L.assign()
     a2 = L.a.cpu().numpy()
-    cptr, ccol, cval = (ex[key].cpu().numpy() for key in ("c_ptr", "c_col", "c_val"))
-    objs = np.sort(rng.choice(corpus.n, 120, replace=False))
-    terms = np.unique(np.concatenate([corpus.col[corpus.row_ptr[i]:corpus.row_ptr[i + 1]] for i in objs]))
-    tix = {int(t): r for r, t in enumerate(terms)}
-    Xs = _rows_dense(corpus, objs, tix)
-    M = np.zeros((len(terms), k))
-    rows_of = np.repeat(np.arange(k), np.diff(cptr))
-    keep = np.isin(ccol, terms)
-    M[np.searchsorted(terms, ccol[keep]), rows_of[keep]] = cval[keep]
-    rho = Xs @ M
-    best = rho.max(1)
-    got = rho[np.arange(len(objs)), a2[objs]]
-    assert np.all(got >= best - 1e-12 * np.maximum(1.0, np.abs(best)))
+    sample = np.sort(rng.choice(corpus.n, 600, replace=False))
+    ref, _, _ = oracle.assign(corpus, cents, rows=sample)
+    assert np.array_equal(a2[sample], ref)
+    lam_ref, moved = oracle.mark_invariant(a1, a2, k, first=False)
+    assert np.array_equal(L.lam.cpu().numpy(), lam_ref) and st["moved"] == moved
+    m_ref = oracle.multadds(corpus, oracle.build_ivf(cents, np.zeros(k, np.uint8)), icp=True,
+                            lam_prev=np.zeros(k, np.uint8), a_prev=a1)
+    assert st["multadds"] == m_ref
