@@ -253,7 +253,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (one GPU per run).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (one GPU per run).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

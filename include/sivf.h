@@ -58,7 +58,7 @@ typedef enum {
     SIVF_E_NONFINITE = -5,   /* NaN or infinity in a value array */
     SIVF_E_NOMEM = -6,       /* device allocation failed or would exceed workspace_cap_bytes */
     SIVF_E_HIP = -7,         /* a HIP runtime call or kernel launch failed */
-    SIVF_E_UNSUPPORTED = -8  /* valid request this build does not support */
+    SIVF_E_UNSUPPORTED = -8  /* valid request this library does not support */
 } sivf_status;
 
 typedef enum { SIVF_F32 = 0, SIVF_F64 = 1, SIVF_BF16 = 2 } sivf_dtype;

@@ -8,7 +8,7 @@ from ._native import LIB_PATH, SivfError, load  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Context", "DeviceCsr", "Ivf", "Lloyd"):
+    if name in ("Context", "DeviceCsr", "Ivf", "Lloyd", "run_lloyd"):
         from . import api
         return getattr(api, name)
     if name == "SoftAssignLoss":

@@ -107,6 +107,11 @@ class Ivf:
         out["p_cid"], out["p_val"] = out["p_cid"][:npost], out["p_val"][:npost]
         return out
 
+    def centroids(self) -> DeviceCsr:
+        """The centroids as a k x D FP64 CSR in device memory (a copy)."""
+        ex = self.export()
+        return DeviceCsr(ex["c_ptr"], ex["c_col"], ex["c_val"], self.sizes()["d"])
+
 
 class Context:
     def __init__(self, device=0, posting_dtype="fp32", filter_mode="sivf", k_tile=0, certify=True,
@@ -240,3 +245,18 @@ class Lloyd:
 
     def update(self):
         return self.ctx.update(self.X, self.a, self.lam, self.ivf)
+
+
+def run_lloyd(X: DeviceCsr, k: int, init_ids, max_iter: int, icp=True, precision="fp32", device=0, **options):
+    """Spherical Lloyd from the given seeds (Alg. 1 around Alg. 4 / Alg. 5).
+
+    icp selects the SIVF filter (else plain IVF, every posting), precision the
+    posting values ("fp32" or "bf16"); the assignments are the same either way.
+    Further keyword options go to Context.  Returns (assign int32[N] on the
+    device, centroids as a FP64 DeviceCsr, per-iteration stats)."""
+    ctx = Context(device, posting_dtype=precision, filter_mode="sivf" if icp else "ivf", **options)
+    a, _, ivf, stats = ctx.run_lloyd(X, k, init_ids, max_iter)
+    C = ivf.centroids()
+    ivf.free()
+    ctx.close()
+    return a, C, stats

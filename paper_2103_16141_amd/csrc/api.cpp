@@ -253,7 +253,7 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     dev_free(ctx, f->cnorm, (size_t)f->k * 8, &f->bytes);
     dev_free(ctx, f->head, (size_t)f->d * 4, &f->bytes);
     dev_free(ctx, f->icp_head, (size_t)f->T, &f->bytes);
-    dev_free(ctx, f->hval, (size_t)f->hcap * f->T * f->kt * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
+    dev_free(ctx, f->hval, (size_t)f->hcap * f->T * head_ktp(f->kt) * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
     delete f;
 }
 
@@ -325,7 +325,7 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
     HIPCHK(ctx, ivf_fill(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, f->cid, f->v32, f->v16, f->v64, ctx->stream));
     f->H = 0;
     if (f->head) {
-        const int64_t kpad = (int64_t)f->T * f->kt, esz = f->pdt == SIVF_BF16 ? 2 : 4;
+        const int64_t kpad = (int64_t)f->T * head_ktp(f->kt), esz = f->pdt == SIVF_BF16 ? 2 : 4;
         // rows beyond the cap are not built: the walk then reads every list
         if (H > 0 && H * kpad * esz <= kHeadCapBytes) {
             if (H > f->hcap) {
@@ -337,7 +337,8 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
                 STCHK(dev_alloc(ctx, &f->hval, (size_t)(c * kpad * esz), &f->bytes));
                 f->hcap = c;
             }
-            HIPCHK(ctx, head_fill(f->cur, f->k, f->head, kpad, H, f->pdt == SIVF_BF16, f->hval, ctx->stream));
+            HIPCHK(ctx, head_fill(f->cur, f->k, f->head, kpad, f->kt, head_ktp(f->kt), H, f->pdt == SIVF_BF16, f->hval,
+                                  ctx->stream));
             HIPCHK(ctx, head_icp_tiles(f->lam, f->k, f->kt, f->T, ctx->opt.icp_head_moving, f->icp_head, ctx->stream));
             f->H = H;
         }
@@ -643,7 +644,7 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.head = f->H > 0 ? f->head : nullptr;
     A.icp_head = f->icp_head;
     A.hval = f->hval;
-    A.kpad = (int64_t)f->T * f->kt;
+    A.kpad = (int64_t)f->T * head_ktp(f->kt);
     A.hbytes = f->H * A.kpad * (f->pdt == SIVF_BF16 ? 2 : 4);
 
     hipStream_t s = ctx->stream;

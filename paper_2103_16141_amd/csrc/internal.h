@@ -77,7 +77,7 @@ struct WalkArgs {
     const int32_t* head;    // [d] row of each term, -1 if none
     const uint8_t* icp_head;  // [T] 1: objects in the ICP branch read head rows in this tile too
     const void* hval;       // [H * kpad] values in the posting dtype
-    int64_t kpad;           // row length: T * kt
+    int64_t kpad;           // row length: T * head_ktp(kt) (each tile padded to 512 slots)
     int64_t hbytes;         // bytes of hval (< 2^32)
     // relaxed ICP (filter mode RELAXED)
     Store st;                  // the current centroids (FP64 CSR) for exact similarities
@@ -183,8 +183,10 @@ hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len,
 hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s);
 hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, float min_moving, uint8_t* icp_ok,
                           hipStream_t s);
-hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int64_t H, int pdt_bf16,
-                     void* hval, hipStream_t s);
+// head-row slots per tile: kt rounded up to whole 512-centroid batches
+inline int32_t head_ktp(int32_t kt) { return (kt + 511) & ~511; }
+hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int32_t kt, int32_t ktp, int64_t H,
+                     int pdt_bf16, void* hval, hipStream_t s);
 hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val,
                       int64_t* ws_counts, int64_t* scan_ws, hipStream_t s);
 hipError_t store_export(const Store st, int32_t k, const int64_t* c_ptr, int32_t* c_col, double* c_val,

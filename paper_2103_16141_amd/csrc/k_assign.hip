@@ -174,57 +174,71 @@ struct DBatch {
     u32x4 a, b;
 };
 
-template <bool BF16>
-__device__ inline DBatch dense_load(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
+// FP32 rows: one 512-centroid batch is two 16-byte loads per lane, centroids
+// 4l..4l+3 and 256+4l..256+4l+3 of the batch
+__device__ inline DBatch dense_load32(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
     DBatch r;
-    if (BF16) {
-        const int so = (int)(uint32_t)(at * 2);
-        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(dd, lane * 8, so, 0);
-        const u32x2 y = __builtin_amdgcn_raw_buffer_load_b64(dd, lane * 8 + 512, so, 0);
-        r.a = u32x4{x.x, x.y, 0u, 0u};
-        r.b = u32x4{y.x, y.y, 0u, 0u};
-    } else {
-        const int so = (int)(uint32_t)(at * 4);
-        r.a = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, so, 0);
-        r.b = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16 + 1024, so, 0);
-    }
+    const int so = (int)(uint32_t)(at * 4);
+    r.a = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, so, 0);
+    r.b = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16 + 1024, so, 0);
     return r;
 }
 
-template <bool BF16>
-__device__ inline void dense_unit(float* sim, u32x4 w, int c0, float xv) {
-    float u0, u1, u2, u3;
-    if (BF16) {
-        u0 = __uint_as_float(w.x << 16);
-        u1 = __uint_as_float(w.x & 0xffff0000u);
-        u2 = __uint_as_float(w.y << 16);
-        u3 = __uint_as_float(w.y & 0xffff0000u);
-    } else {
-        u0 = __uint_as_float(w.x);
-        u1 = __uint_as_float(w.y);
-        u2 = __uint_as_float(w.z);
-        u3 = __uint_as_float(w.w);
-    }
+// BF16 rows are stored interleaved per 512-centroid batch: one 16-byte load
+// per lane gives the same two 4-centroid groups (.x .y, then .z .w)
+__device__ inline u32x4 dense_load16(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
+    return __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, (int)(uint32_t)(at * 2), 0);
+}
+
+__device__ inline void dense_unit32(float* sim, u32x4 w, int c0, float xv) {
     float4* q = (float4*)(sim + c0);
     float4 o = *q;
-    o.x = o.x + xv * u0;
-    o.y = o.y + xv * u1;
-    o.z = o.z + xv * u2;
-    o.w = o.w + xv * u3;
+    o.x = o.x + xv * __uint_as_float(w.x);
+    o.y = o.y + xv * __uint_as_float(w.y);
+    o.z = o.z + xv * __uint_as_float(w.z);
+    o.w = o.w + xv * __uint_as_float(w.w);
     *q = o;
 }
 
 // sim[ub + c] += xv * row[ub + c] for the batch's centroids below kt
-template <bool BF16>
-__device__ inline void dense_accumulate(float* sim, const DBatch& b, int ub, int kt, float xv, int lane) {
+__device__ inline void dense_accumulate32(float* sim, const DBatch& b, int ub, int kt, float xv, int lane) {
     const int c0 = ub + 4 * lane, c1 = ub + 256 + 4 * lane;
     if (ub + 512 <= kt) {
-        dense_unit<BF16>(sim, b.a, c0, xv);
-        dense_unit<BF16>(sim, b.b, c1, xv);
+        dense_unit32(sim, b.a, c0, xv);
+        dense_unit32(sim, b.b, c1, xv);
     } else {
-        // tile width not a multiple of 512: the lanes past it hold other centroids
-        if (c0 < kt) dense_unit<BF16>(sim, b.a, c0, xv);
-        if (c1 < kt) dense_unit<BF16>(sim, b.b, c1, xv);
+        // tile width not a multiple of 512: the lanes past it hold no centroid
+        if (c0 < kt) dense_unit32(sim, b.a, c0, xv);
+        if (c1 < kt) dense_unit32(sim, b.b, c1, xv);
+    }
+}
+
+// two head terms in one read-add-write of four similarities: the additions
+// keep the order of two separate passes (first term, then second)
+__device__ inline void dense_unit16x2(float* sim, uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1, int c0,
+                                      float xa, float xb) {
+    float4* q = (float4*)(sim + c0);
+    float4 o = *q;
+    o.x = o.x + xa * __uint_as_float(a0 << 16);
+    o.y = o.y + xa * __uint_as_float(a0 & 0xffff0000u);
+    o.z = o.z + xa * __uint_as_float(a1 << 16);
+    o.w = o.w + xa * __uint_as_float(a1 & 0xffff0000u);
+    o.x = o.x + xb * __uint_as_float(b0 << 16);
+    o.y = o.y + xb * __uint_as_float(b0 & 0xffff0000u);
+    o.z = o.z + xb * __uint_as_float(b1 << 16);
+    o.w = o.w + xb * __uint_as_float(b1 & 0xffff0000u);
+    *q = o;
+}
+
+__device__ inline void dense_accumulate16x2(float* sim, u32x4 wa, u32x4 wb, int ub, int kt, float xa, float xb,
+                                            int lane) {
+    const int c0 = ub + 4 * lane, c1 = ub + 256 + 4 * lane;
+    if (ub + 512 <= kt) {
+        dense_unit16x2(sim, wa.x, wa.y, wb.x, wb.y, c0, xa, xb);
+        dense_unit16x2(sim, wa.z, wa.w, wb.z, wb.w, c1, xa, xb);
+    } else {
+        if (c0 < kt) dense_unit16x2(sim, wa.x, wa.y, wb.x, wb.y, c0, xa, xb);
+        if (c1 < kt) dense_unit16x2(sim, wa.z, wa.w, wb.z, wb.w, c1, xa, xb);
     }
 }
 
@@ -282,6 +296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int kts = A.kt + 64;   // tile plus one spare slot per lane
+    const int ktp = (A.kt + 511) & ~511;   // a tile's slots in a head row
     float* sim = lds + wid * kts;
     int32_t* cj = (int32_t*)(lds + kWalkWaves * kts) + wid * kCandCap;
     float* cr = (float*)((int32_t*)(lds + kWalkWaves * kts) + kWalkWaves * kCandCap) + wid * kCandCap;
@@ -426,12 +441,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const bool use_head = A.head && (!filt || (!CB && A.icp_head[tile]));
                 if (use_head && h < n) hrow = h < kTermCap ? th[h] : A.head[A.col[r0 + h]];
                 unsigned long long dl = ballot(hrow >= 0);
-                if (dl) {
+                const int64_t hb = (int64_t)tile * ktp;   // the tile's slots in a head row
+                if (dl && BF16) {
+                    // two terms per pass over the tile (a lone last term is paired
+                    // with its own row at weight 0, which adds +-0 exactly)
+                    float pa = 0.0f, pb = 0.0f;
+                    int64_t ra = 0, rz = 0;
+                    auto take = [&]() -> bool {
+                        if (!dl) return false;
+                        int q = __builtin_ctzll(dl);
+                        dl &= dl - 1;
+                        pa = bcast_f32(v, q);
+                        ra = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        pb = 0.0f;
+                        rz = ra;
+                        if (dl) {
+                            q = __builtin_ctzll(dl);
+                            dl &= dl - 1;
+                            pb = bcast_f32(v, q);
+                            rz = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        }
+                        return true;
+                    };
+                    take();
+                    int ub = 0;
+                    auto padv = [&]() -> bool {
+                        ub += 512;
+                        if (ub < A.kt) return true;
+                        ub = 0;
+                        return take();
+                    };
+                    u32x4 Xa = dense_load16(dd, ra + ub, lane), Xb = dense_load16(dd, rz + ub, lane), Ya, Yb;
+                    int xu = ub, yu = 0;
+                    float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
+                    for (;;) {
+                        if (!padv()) {
+                            dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
+                            break;
+                        }
+                        Ya = dense_load16(dd, ra + ub, lane);
+                        Yb = dense_load16(dd, rz + ub, lane);
+                        yu = ub;
+                        ya = pa;
+                        yb = pb;
+                        dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
+                        if (!padv()) {
+                            dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
+                            break;
+                        }
+                        Xa = dense_load16(dd, ra + ub, lane);
+                        Xb = dense_load16(dd, rz + ub, lane);
+                        xu = ub;
+                        xa = pa;
+                        xb = pb;
+                        dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
+                    }
+                } else if (dl) {
                     int q = __builtin_ctzll(dl);
                     dl &= dl - 1;
                     int ub = 0;
                     float xv = bcast_f32(v, q);
-                    int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + base;
+                    int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
                     auto dadv = [&]() -> bool {
                         ub += 512;
                         if (ub < A.kt) return true;
@@ -440,29 +510,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         dl &= dl - 1;
                         ub = 0;
                         xv = bcast_f32(v, q);
-                        rb = (int64_t)bcast_i32(hrow, q) * A.kpad + base;
+                        rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
                         return true;
                     };
-                    DBatch X = dense_load<BF16>(dd, rb + ub, lane), Y;
+                    DBatch X = dense_load32(dd, rb + ub, lane), Y;
                     int xu = ub, yu = 0;
                     float xx = xv, yx = 0.0f;
                     for (;;) {
                         if (!dadv()) {
-                            dense_accumulate<BF16>(sim, X, xu, A.kt, xx, lane);
+                            dense_accumulate32(sim, X, xu, A.kt, xx, lane);
                             break;
                         }
-                        Y = dense_load<BF16>(dd, rb + ub, lane);
+                        Y = dense_load32(dd, rb + ub, lane);
                         yu = ub;
                         yx = xv;
-                        dense_accumulate<BF16>(sim, X, xu, A.kt, xx, lane);
+                        dense_accumulate32(sim, X, xu, A.kt, xx, lane);
                         if (!dadv()) {
-                            dense_accumulate<BF16>(sim, Y, yu, A.kt, yx, lane);
+                            dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
                             break;
                         }
-                        X = dense_load<BF16>(dd, rb + ub, lane);
+                        X = dense_load32(dd, rb + ub, lane);
                         xu = ub;
                         xx = xv;
-                        dense_accumulate<BF16>(sim, Y, yu, A.kt, yx, lane);
+                        dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
                     }
                 }
                 // ---- other terms: structured lists

@@ -152,10 +152,23 @@ hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T,
 
 // ---------------------------------------------------------------- dense head rows
 // A memory layout of this implementation (not the paper's): a term whose
-// lists hold at least min_len postings gets a row of kpad = T * kt values,
+// lists hold at least min_len postings gets a row of kpad = T * ktp values,
 // one per centroid id (zero where the centroid lacks the term), rounded to
 // the posting dtype exactly as its postings are.  Rows are numbered in term
-// order.
+// order.  Each tile's kt centroids take ktp = kt rounded up to 512 slots.
+// FP32 rows hold the tile's centroids in order.  BF16 rows interleave each
+// 512-centroid block so that one 16-byte load gives a lane both of its
+// 4-centroid groups: slots 8l..8l+3 hold centroids 4l..4l+3 of the block,
+// slots 8l+4..8l+7 centroids 256+4l..256+4l+3.
+__device__ inline int64_t head_slot(int32_t j, int32_t kt, int32_t ktp, bool bf16) {
+    const int32_t tile = j / kt, jj = j - tile * kt;
+    int32_t at = jj;
+    if (bf16) {
+        const int32_t i = jj & 511;
+        at = (jj & ~511) + 8 * ((i & 255) >> 2) + 4 * (i >> 8) + (i & 3);
+    }
+    return (int64_t)tile * ktp + at;
+}
 __global__ void k_head_flags(const int64_t* __restrict__ seg, int64_t d, int32_t T, int64_t min_len,
                              int64_t* __restrict__ flag) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -176,8 +189,8 @@ __global__ void k_head_zero(uint32_t* __restrict__ w, int64_t nw) {
 }
 
 // one wave per centroid: scatter its head-term values into the rows
-__global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ head, int64_t kpad,
-                               float* __restrict__ h32, uint16_t* __restrict__ h16) {
+__global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ head, int64_t kpad, int32_t kt,
+                               int32_t ktp, float* __restrict__ h32, uint16_t* __restrict__ h16) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -187,8 +200,8 @@ __global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ 
             const int32_t r = head[st.term[b + p]];
             if (r >= 0) {
                 const float f = (float)st.val[b + p];  // round to nearest even
-                if (h32) h32[r * kpad + j] = f;
-                else h16[r * kpad + j] = f32_to_bf16_rne(f);
+                if (h32) h32[r * kpad + head_slot((int32_t)j, kt, ktp, false)] = f;
+                else h16[r * kpad + head_slot((int32_t)j, kt, ktp, true)] = f32_to_bf16_rne(f);
             }
         }
     }
@@ -230,8 +243,8 @@ hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32
     return hipGetLastError();
 }
 
-hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int64_t H, int pdt_bf16,
-                     void* hval, hipStream_t s) {
+hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int32_t kt, int32_t ktp, int64_t H,
+                     int pdt_bf16, void* hval, hipStream_t s) {
     const int64_t bytes = H * kpad * (pdt_bf16 ? 2 : 4);
     const int64_t nw = (bytes + 3) / 4;
     if (nw == 0) return hipSuccess;
@@ -242,7 +255,7 @@ hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpa
     if (e != hipSuccess) return e;
     int64_t blocks = ((int64_t)k * 64 + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_head_scatter, dim3((unsigned)blocks), dim3(256), 0, s, st, k, head, kpad,
+    hipLaunchKernelGGL(k_head_scatter, dim3((unsigned)blocks), dim3(256), 0, s, st, k, head, kpad, kt, ktp,
                        pdt_bf16 ? nullptr : (float*)hval, pdt_bf16 ? (uint16_t*)hval : nullptr);
     return hipGetLastError();
 }

@@ -126,6 +126,14 @@ def test_run_lloyd_matches_stepwise_and_is_deterministic():
     assert len(st1) == tr.iters
     assert np.array_equal(a1.cpu().numpy(), tr.assign[-1])
     assert [s["multadds"] for s in st1] == tr.multadds
+    # the module-level convenience call: same assignments, centroids as CSR
+    from paper_2103_16141_amd import run_lloyd
+    for precision, icp in (("bf16", True), ("fp32", False)):
+        a3, C3, st3 = run_lloyd(X, 120, ids, 20, icp=icp, precision=precision)
+        assert np.array_equal(a3.cpu().numpy(), tr.assign[-1])
+        assert len(st3) == tr.iters
+        assert torch.equal(C3.row_ptr, e1["c_ptr"]) and torch.equal(C3.col, e1["c_col"])
+        assert torch.equal(C3.val, e1["c_val"]) and C3.n_cols == c.d
 
 
 @pytest.mark.parametrize("posting", ["fp32", "bf16"])
