@@ -245,6 +245,7 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     }
     dev_free(ctx, f->seg, (size_t)(f->d * f->T + 1) * 8, &f->bytes);
     dev_free(ctx, f->mid, (size_t)(f->d * f->T) * 4, &f->bytes);
+    dev_free(ctx, f->rec, (size_t)(f->d * f->T) * 16, &f->bytes);
     dev_free(ctx, f->cid, (size_t)f->pcap * 2, &f->bytes);
     dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
     dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
@@ -271,6 +272,7 @@ sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
     }
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->seg, (size_t)(d * f->T + 1) * 8, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mid, (size_t)(d * f->T) * 4, &f->bytes);
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->rec, (size_t)(d * f->T) * 16, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->lam, (size_t)k, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->cnorm, (size_t)k * 8, &f->bytes);
     if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->head, (size_t)d * 4, &f->bytes);
@@ -343,6 +345,7 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
             f->H = H;
         }
     }
+    HIPCHK(ctx, seg_records(f->seg, f->mid, f->H > 0 ? f->head : nullptr, f->d, f->T, f->rec, ctx->stream));
     if (!f->nonneg) HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
     return SIVF_OK;
 }
@@ -597,6 +600,8 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.T = f->T;
     A.seg = f->seg;
     A.mid = f->mid;
+    A.rec = f->rec;
+    A.d = f->d;
     A.cid = f->cid;
     A.pval = f->pdt == SIVF_BF16 ? (const void*)f->v16 : (const void*)f->v32;
     A.lam = f->lam;

@@ -49,6 +49,9 @@ struct WalkArgs {
     int32_t k, kt, T;
     const int64_t* seg;     // [d*T + 1] segment starts, segment (t, tile) = t*T + tile
     const int32_t* mid;     // [d*T] moving-part length of each segment
+    const uint4* rec;       // [T*d] record of segment (t, tile) at tile*d + t: start (lo, hi),
+                            // length | moving length << 16, dense head row or -1
+    int64_t d;
     const uint16_t* cid;    // tile-local centroid ids
     const void* pval;       // f32 or bf16 posting values
     const uint8_t* lam;     // flags the file is structured by (lambda^[r-1])
@@ -104,6 +107,7 @@ struct sivf_ivf {
     sivf::Store cur, nxt;           // current centroids, and the buffer the next update writes
     int64_t* seg = nullptr;         // [d*T + 1]
     int32_t* mid = nullptr;         // [d*T]
+    uint4* rec = nullptr;           // [T*d] tile-major segment records read by the walk
     uint16_t* cid = nullptr;        // [pcap]
     float* v32 = nullptr;           // [pcap] (posting dtype f32)
     uint16_t* v16 = nullptr;        // [pcap] (posting dtype bf16)
@@ -180,6 +184,8 @@ hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T,
                     IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s);
 // dense head rows: flag[t] = 1 if term t's lists hold >= min_len postings
 hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s);
+hipError_t seg_records(const int64_t* seg, const int32_t* mid, const int32_t* head, int64_t d, int32_t T, uint4* rec,
+                       hipStream_t s);
 hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s);
 hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, float min_moving, uint8_t* icp_ok,
                           hipStream_t s);

@@ -302,7 +302,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     float* cr = (float*)((int32_t*)(lds + kWalkWaves * kts) + kWalkWaves * kCandCap) + wid * kCandCap;
     int32_t* tt = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap)) + wid * kTermCap;
     float* tv = lds + kWalkWaves * (kts + 2 * kCandCap + kTermCap) + wid * kTermCap;
-    int32_t* th = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap + 2 * kTermCap)) + wid * kTermCap;
     const __amdgpu_buffer_rsrc_t dd = span_rsrc(A.hval, A.hbytes);
 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
@@ -386,28 +385,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const int32_t t = A.col[r0 + h];
                 tt[h] = t;
                 tv[h] = load_xval(A.xval, A.x_f64, r0 + h);
-                th[h] = A.head ? A.head[t] : -1;
             }
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
             const int nch = max(1, (n + 63) >> 6);
             const int npairs = (te - tb) * nch;
-            int64_t ns0 = 0, ns1 = 0;
-            int32_t nmv = 0;
-            // segment bounds of pair pi, issued one pair ahead of their use
+            int64_t ns0 = 0;
+            int32_t nlen = 0, nmv = 0, nhr = -1;
+            // segment record of pair pi (start, length, moving length, head
+            // row), issued one pair ahead of its use
             auto seg_load = [&](int pi) {
                 const int rel = pi / nch;   // tile index within this launch
                 const int tl = tb + rel;
                 const int h = (pi - rel * nch) * 64 + lane;
                 ns0 = 0;
-                ns1 = 0;
+                nlen = 0;
                 nmv = 0;
+                nhr = -1;
                 if (h < n) {
                     const int64_t t = h < kTermCap ? (int64_t)tt[h] : (int64_t)A.col[r0 + h];
-                    const int64_t sidx = t * A.T + tl;
-                    ns0 = A.seg[sidx];
-                    ns1 = A.seg[sidx + 1];
-                    nmv = A.mid[sidx];
+                    const uint4 r = A.rec[(int64_t)tl * A.d + t];
+                    ns0 = (int64_t)(((uint64_t)r.y << 32) | r.x);
+                    nlen = (int32_t)(r.z & 0xffffu);
+                    nmv = (int32_t)(r.z >> 16);
+                    nhr = (int32_t)r.w;
                 }
             };
             seg_load(0);
@@ -417,8 +418,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const int32_t base = tile * A.kt;
                 const int32_t width = min(A.kt, A.k - base);
                 const int64_t s0 = ns0;
-                const int64_t e = front_only ? s0 + nmv : ns1;
+                const int64_t e = s0 + (front_only ? nmv : nlen);
                 const int32_t mv = nmv;
+                const int32_t hr = nhr;
                 if (pi + 1 < npairs) seg_load(pi + 1);
                 const int h = ch * 64 + lane;
                 float v = 0.0f;
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 // flight while the current one is accumulated
                 int hrow = -1;
                 const bool use_head = A.head && (!filt || (!CB && A.icp_head[tile]));
-                if (use_head && h < n) hrow = h < kTermCap ? th[h] : A.head[A.col[r0 + h]];
+                if (use_head && h < n) hrow = hr;
                 unsigned long long dl = ballot(hrow >= 0);
                 const int64_t hb = (int64_t)tile * ktp;   // the tile's slots in a head row
                 if (dl && BF16) {
@@ -747,9 +749,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
 }
 
 // per wave: the similarity tile and its 64 spare slots, the candidate list
-// (ids, values) and the staged terms (id, value, head row)
+// (ids, values) and the staged terms (id, value)
 static size_t walk_lds_bytes(int kt) {
-    return (size_t)kWalkWaves * ((size_t)kt + 64 + 2 * kCandCap + 3 * kTermCap) * sizeof(float);
+    return (size_t)kWalkWaves * ((size_t)kt + 64 + 2 * kCandCap + 2 * kTermCap) * sizeof(float);
 }
 
 // The four instantiations: posting precision x (SIVF | IVF-CBICP filter).

@@ -233,6 +233,35 @@ hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, 
     return hipGetLastError();
 }
 
+// Tile-major copy of the segment bounds for the walk: one 16-byte record per
+// (tile, term) holding the segment start, its length and moving length (each
+// at most kt <= 4096, so 16 bits apiece) and the term's dense head row (-1:
+// none, or head == nullptr).  A launch over one tile then reads a 16*d-byte
+// slice with one load per term instead of three scattered over the whole
+// term-major table.
+__global__ void k_seg_records(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid,
+                              const int32_t* __restrict__ head, int64_t d, int32_t T, uint4* __restrict__ rec) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= d * T) return;
+    const int64_t tile = idx / d, t = idx - tile * d;
+    const int64_t s0 = seg[t * T + tile], len = seg[t * T + tile + 1] - s0;
+    const uint32_t mv = (uint32_t)mid[t * T + tile];
+    uint4 r;
+    r.x = (uint32_t)(uint64_t)s0;
+    r.y = (uint32_t)((uint64_t)s0 >> 32);
+    r.z = (uint32_t)len | (mv << 16);
+    r.w = (uint32_t)(head ? head[t] : -1);
+    rec[idx] = r;
+}
+
+hipError_t seg_records(const int64_t* seg, const int32_t* mid, const int32_t* head, int64_t d, int32_t T, uint4* rec,
+                       hipStream_t s) {
+    const int64_t n = d * T;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_records, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seg, mid, head, d, T, rec);
+    return hipGetLastError();
+}
+
 hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_head_flags, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, seg, d, T, min_len, flag);
     return hipGetLastError();
