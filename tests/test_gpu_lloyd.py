@@ -159,6 +159,33 @@ def test_dense_head_rows_same_trajectory(posting, k, k_tile):
     assert all(a >= b for a, b in zip(rows[0.1], rows[1.0]))
 
 
+@pytest.mark.parametrize("posting", ["fp32", "bf16"])
+def test_widest_tile_full_length_segments(posting):
+    # The largest tile (4096 centroids) and a term every object holds: its
+    # list segment in a tile is as long as the tile, the longest a segment
+    # record describes.  k = 4500 leaves a ragged second tile of 404.  Lists
+    # only (no dense rows) and with dense rows.
+    log("widest tile, full-length segments, posting=%s" % posting)
+    c0 = synth.make_corpus(9000, 800, 12, 1.0, np.float32, seed=109)
+    rows, vals = [], []
+    for i in range(c0.n):
+        t = c0.col[c0.row_ptr[i]:c0.row_ptr[i + 1]].tolist()
+        v = c0.val[c0.row_ptr[i]:c0.row_ptr[i + 1]].astype(np.float64)
+        if t[0] != 0:
+            t = [0] + t
+            v = np.concatenate([[0.3], v])
+        v = v / np.linalg.norm(v)
+        rows.append(t)
+        vals.append(v.astype(np.float32).tolist())
+    c = corpus_from_rows(rows, c0.d, vals, np.float32)
+    ids = synth.init_ids(c.n, 4500, 15)
+    for hd in (0.0, 0.5):
+        ctx = _ctx(k_tile=4096, posting_dtype=posting, head_density=hd)
+        tr, st = lloyd_parity(ctx, _X(c), c, 4500, ids, 4)
+        assert (max(s["head_rows"] for s in st) > 0) == (hd > 0)
+        ctx.close()
+
+
 @pytest.mark.parametrize("tiles_per_launch", [1, 2, 64])
 def test_tile_launch_split_with_ties_and_overflow(tiles_per_launch):
     # 100 identical seeds spread over five 64-centroid tiles: objects near them
