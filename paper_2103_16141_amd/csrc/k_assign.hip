@@ -390,26 +390,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
             // empty row still has one pair per tile so every tile is closed.
             const int nch = max(1, (n + 63) >> 6);
             const int npairs = (te - tb) * nch;
-            int64_t ns0 = 0;
-            int32_t nlen = 0, nmv = 0, nhr = -1;
-            // segment record of pair pi (start, length, moving length, head
-            // row), issued one pair ahead of its use
+            // segment record and object value of pair pi, issued one pair ahead
+            // of their use and decoded only there: every lane loads (terms past
+            // the row read term 0's record), so no condition makes the compiler
+            // wait for the load right away
+            uint4 nrec = {0u, 0u, 0u, 0u};
+            bool nin = false;
+            float nv = 0.0f;
             auto seg_load = [&](int pi) {
                 const int rel = pi / nch;   // tile index within this launch
                 const int tl = tb + rel;
-                const int h = (pi - rel * nch) * 64 + lane;
-                ns0 = 0;
-                nlen = 0;
-                nmv = 0;
-                nhr = -1;
-                if (h < n) {
-                    const int64_t t = h < kTermCap ? (int64_t)tt[h] : (int64_t)A.col[r0 + h];
-                    const uint4 r = A.rec[(int64_t)tl * A.d + t];
-                    ns0 = (int64_t)(((uint64_t)r.y << 32) | r.x);
-                    nlen = (int32_t)(r.z & 0xffffu);
-                    nmv = (int32_t)(r.z >> 16);
-                    nhr = (int32_t)r.w;
+                const int hb = (pi - rel * nch) * 64;
+                const int h = hb + lane;
+                nin = h < n;
+                int32_t t;
+                float xv;
+                if (hb < kTermCap) {   // staged terms (hb + lane < kTermCap)
+                    t = tt[hb + lane];
+                    xv = tv[hb + lane];
+                } else {               // rows longer than kTermCap: n > hb
+                    const int64_t hc = r0 + min(h, n - 1);
+                    t = A.col[hc];
+                    xv = load_xval(A.xval, A.x_f64, hc);
                 }
+                nrec = A.rec[(int64_t)tl * A.d + (nin ? t : 0)];
+                nv = nin ? xv : 0.0f;
             };
             seg_load(0);
             for (int pi = 0; pi < npairs; ++pi) {
@@ -417,17 +422,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const int ch = pi - (tile - tb) * nch;
                 const int32_t base = tile * A.kt;
                 const int32_t width = min(A.kt, A.k - base);
-                const int64_t s0 = ns0;
-                const int64_t e = s0 + (front_only ? nmv : nlen);
-                const int32_t mv = nmv;
-                const int32_t hr = nhr;
+                const uint4 rr = nrec;
+                const bool in = nin;
+                const float v = nv;
                 if (pi + 1 < npairs) seg_load(pi + 1);
+                const int64_t s0 = in ? (int64_t)(((uint64_t)rr.y << 32) | rr.x) : 0;
+                const int32_t mv = in ? (int32_t)(rr.z >> 16) : 0;
+                const int64_t e = s0 + (in ? (front_only ? mv : (int32_t)(rr.z & 0xffffu)) : 0);
+                const int32_t hr = in ? (int32_t)rr.w : -1;
                 const int h = ch * 64 + lane;
-                float v = 0.0f;
-                if (h < n) {
-                    v = h < kTermCap ? tv[h] : load_xval(A.xval, A.x_f64, r0 + h);
-                    macc += test_flag ? (unsigned long long)mv : (unsigned long long)(e - s0);
-                }
+                if (in) macc += test_flag ? (unsigned long long)mv : (unsigned long long)(e - s0);
                 // ---- walk the non-empty lists of this chunk in ascending term
                 // order, kBatch postings per batch (a batch never spans two
                 // lists); the next batch's loads are in flight while the
