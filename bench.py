@@ -5,8 +5,9 @@ Alg. 4 / Alg. 5) of the whole path on the headline workload: N = 8,000,000
 L2-normalised sparse rows, D = 140,000 terms, nnz/row ~ Poisson(90), Zipf(1.1)
 term ids, lognormal values (seeded synthetic stand-in for the paper's 8M
 PubMed subset), k = 10,000 seeded initial centroids.  The timed region is
-iterations 1..K of a fresh run from the seeded initial state (W untimed warmup
-iterations are run first on a separate run from the same state).
+iterations 1..K of a fresh run from the seeded initial state (default K = 30,
+the run length of this workload; W untimed warmup iterations are run first on
+a separate run from the same state).
 
 Reported value: assignment-step object-centroid mult-adds per second with FP32
 postings (sum of posting mult-adds over the timed iterations divided by the
@@ -224,7 +225,7 @@ def cpu_baseline(corpus, ids, k, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--n", type=int, default=None, help="override N (smaller runs for development)")
     ap.add_argument("--skip-bf16", action="store_true")
