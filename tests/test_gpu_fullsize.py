@@ -14,6 +14,8 @@ N = 8M objects, D = 140k, k = 10k, automatic tiles (the headline workload):
 Soft form at its full shape (N = 262,144, D = 100k, k = 4,096): sampled rows'
 lse and dX and sampled columns of dC against the oracle; the dC column-sum
 identity over all columns.
+N = 1M, D = 100k, k = 1,000 run to convergence or 50 iterations, each
+iteration one step against the oracle.
 NYT-shaped corpus (N = 1,285,944, D = 495,714, ~226 nonzeros per row, k =
 10k): iteration 1 on sampled objects against the oracle; update 1 bit for bit
 against the oracle's update of the GPU's assignment; iteration 2 on sampled
@@ -138,6 +140,52 @@ def test_headline_filter_modes_agree(headline):
     assert all(r <= s for r, s in zip(res["relaxed", "fp32"][1], base[1]))
     assert base[2][2] > 0 and res["ivf", "fp32"][2][2] == 0
     assert res["relaxed", "fp32"][2][2] >= base[2][2]
+
+
+def test_config_1m_to_convergence():
+    """N = 1M, D = 100k, Poisson(100), k = 1,000, run to convergence (no
+    assignment change) or 50 iterations, every iteration checked one step at a
+    time against the oracle: flags, moved count and the exact mult-add count
+    over all objects, 2,000 sampled assignments, and the oracle's update of the
+    GPU's assignment bitwise against the GPU's centroids."""
+    from paper_2103_16141_amd.api import Context, DeviceCsr, Lloyd
+    log("generating the 1M x 100k corpus")
+    corpus, ids, w = synth.workload("1m-f32")
+    k = w["k"]
+    X = DeviceCsr.from_corpus(corpus, torch.device("cuda", 0))
+    ctx = Context(0)
+    L = Lloyd(ctx, X, k, ids)
+    rng = np.random.default_rng(7)
+    cents = oracle.init_centroids(corpus, ids)
+    a_prev = lam_prev = None
+    converged = False
+    for r in range(1, w["iters"] + 1):
+        st = L.assign()
+        a = L.a.cpu().numpy()
+        lam = L.lam.cpu().numpy()
+        sample = np.sort(rng.choice(corpus.n, 2000, replace=False))
+        ref, _, _ = oracle.assign(corpus, cents, rows=sample)
+        bad = np.nonzero(a[sample] != ref)[0]
+        assert len(bad) == 0, "iteration %d: sampled objects %s differ" % (r, sample[bad][:5])
+        lam_ref, moved = oracle.mark_invariant(a_prev, a, k, first=(r == 1))
+        assert np.array_equal(lam, lam_ref) and st["moved"] == moved, "iteration %d: flags or moved" % r
+        m_ref = oracle.multadds(corpus, oracle.build_ivf(cents, lam_prev), icp=(r >= 2), lam_prev=lam_prev,
+                                a_prev=a_prev)
+        assert st["multadds"] == m_ref, "iteration %d: multadds %d vs %d" % (r, st["multadds"], m_ref)
+        if r >= 2 and moved == 0:
+            converged = True
+            assert st["multadds"] == 0
+            break
+        L.update()
+        cents, _ = oracle.update(corpus, a, cents)
+        ex, got = _export_centroids(L.ivf)
+        assert np.array_equal(got["c_ptr"], cents.ptr), "update %d: centroid sizes differ" % r
+        assert np.array_equal(got["c_col"], cents.col), "update %d: centroid supports differ" % r
+        assert np.array_equal(got["c_val"], cents.val), "update %d: centroid values differ" % r
+        del ex, got
+        a_prev, lam_prev = a, lam
+    log("stopped after iteration %d (converged: %s)" % (r, converged))
+    ctx.close()
 
 
 def test_soft_fullsize_sampled():
