@@ -14,6 +14,8 @@ N = 8M objects, D = 140k, k = 10k, automatic tiles (the headline workload):
 Soft form at its full shape (N = 262,144, D = 100k, k = 4,096): sampled rows'
 lse and dX and sampled columns of dC against the oracle; the dC column-sum
 identity over all columns.
+The precision form at N = 8M, k = 20,000 with BF16 postings: iterations 1-3
+one step at a time against the oracle.
 N = 1M, D = 100k, k = 1,000 run to convergence or 50 iterations, each
 iteration one step against the oracle.
 NYT-shaped corpus (N = 1,285,944, D = 495,714, ~226 nonzeros per row, k =
@@ -120,6 +122,48 @@ def test_headline_one_step_parity(headline):
         del ex, got
         a_prev, lam_prev = a, lam
     ctx.close()
+
+
+def test_precision_form_k20k_one_step_parity():
+    """The precision form at its own configuration (N = 8M, D = 140k,
+    k = 20,000, BF16 postings): iterations 1-3 one step at a time against the
+    oracle, as for the headline workload."""
+    from paper_2103_16141_amd.api import Context, DeviceCsr, Lloyd
+    log("generating the 8M x 140k corpus for k = 20,000")
+    corpus, ids, w = synth.workload("8m-bf16-k20k")
+    k = w["k"]
+    X = DeviceCsr.from_corpus(corpus, torch.device("cuda", 0))
+    ctx = Context(0, posting_dtype="bf16")
+    L = Lloyd(ctx, X, k, ids)
+    rng = np.random.default_rng(11)
+    cents = oracle.init_centroids(corpus, ids)
+    a_prev = lam_prev = None
+    for r in range(1, 4):
+        log("iteration %d" % r)
+        st = L.assign()
+        a = L.a.cpu().numpy()
+        lam = L.lam.cpu().numpy()
+        sample = np.sort(rng.choice(corpus.n, 1000, replace=False))
+        ref, _, _ = oracle.assign(corpus, cents, rows=sample)
+        bad = np.nonzero(a[sample] != ref)[0]
+        assert len(bad) == 0, "iteration %d: sampled objects %s differ" % (r, sample[bad][:5])
+        lam_ref, moved = oracle.mark_invariant(a_prev, a, k, first=(r == 1))
+        assert np.array_equal(lam, lam_ref) and st["moved"] == moved
+        m_ref = oracle.multadds(corpus, oracle.build_ivf(cents, lam_prev), icp=(r >= 2), lam_prev=lam_prev,
+                                a_prev=a_prev)
+        assert st["multadds"] == m_ref
+        assert st["rescored_objects"] > 0   # BF16 needs the FP64 re-score
+        L.update()
+        cents, _ = oracle.update(corpus, a, cents)
+        ex, got = _export_centroids(L.ivf)
+        assert np.array_equal(got["c_ptr"], cents.ptr)
+        assert np.array_equal(got["c_col"], cents.col)
+        assert np.array_equal(got["c_val"], cents.val)
+        del ex, got
+        a_prev, lam_prev = a, lam
+    ctx.close()
+    del X
+    torch.cuda.empty_cache()
 
 
 def test_headline_filter_modes_agree(headline):
