@@ -15,6 +15,7 @@ namespace sivf {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kCandCap = 32;       // candidate-list capacity per object in the fast pass
 constexpr int kTermCap = 128;      // object terms staged in LDS per wave by the fast pass (the rest read from X)
+static_assert(kTermCap % 64 == 0, "the walk reads staged terms a whole 64-term chunk at a time");
 constexpr int64_t kHeadCapBytes = 0xF0000000LL;   // dense head rows beyond this are not built
 constexpr int kWalkWaves = 4;      // waves per workgroup in the walk kernels
 constexpr int kMaxTile = 4096;     // largest similarity tile (centroids) per wave

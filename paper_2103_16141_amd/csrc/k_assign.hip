@@ -166,8 +166,9 @@ __device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Bat
 
 // Dense head rows: 512 consecutive centroids of one row per batch, lane l
 // holding centroids 4l .. 4l+3 and 256 + 4l .. 256 + 4l+3 (two 16-byte loads
-// for binary32, two 8-byte loads for bf16), so each lane's LDS update is two
-// aligned 16-byte read-add-writes, conflict-free across the wave.
+// for binary32; one 16-byte load for bf16, whose rows store each lane's eight
+// values side by side), so each lane's LDS update is two aligned 16-byte
+// read-add-writes, conflict-free across the wave.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct DBatch {
