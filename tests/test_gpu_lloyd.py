@@ -101,7 +101,9 @@ def test_long_rows_over_64_terms():
 
 
 def test_rows_longer_than_the_staged_terms():
-    # rows of ~300 terms: terms past the 256 staged in LDS are read from X
+    # rows of ~300 terms: the walk reads terms past the 128 it stages in LDS
+    # from X, and the update reads nonzeros past the 256 it holds in registers
+    # chunk by chunk
     log("edge: rows longer than 256 terms")
     c = synth.make_corpus(1500, 4000, 300, 0.9, np.float32, seed=111)
     assert np.diff(c.row_ptr).max() > 256
