@@ -188,6 +188,16 @@ def test_widest_tile_full_length_segments(posting):
         ctx.close()
 
 
+def test_more_than_65536_centroids():
+    # k = 70,000: 69 tiles of 1024 (centroid ids are 16-bit and tile-local,
+    # so the file holds any k); most clusters have one or two members.
+    log("k = 70,000")
+    c = synth.make_corpus(75000, 4000, 8, 1.0, np.float32, seed=112)
+    ids = synth.init_ids(c.n, 70000, 18)
+    tr, st = lloyd_parity(_ctx(), _X(c), c, 70000, ids, 2, check_ivf_every=2)
+    assert tr.iters == 2
+
+
 @pytest.mark.parametrize("tiles_per_launch", [1, 2, 64])
 def test_tile_launch_split_with_ties_and_overflow(tiles_per_launch):
     # 100 identical seeds spread over five 64-centroid tiles: objects near them
