@@ -123,7 +123,15 @@ typedef struct {
                                    invariant ones are not eligible for them) in tiles
                                    where at least this fraction of the centroids is
                                    moving, else the moving part of the lists; > 1
-                                   never.  Same results and mult-add counts. */
+                                   never.  Same results and mult-add counts.
+                                   (Used when icp_compact is 0.) */
+    int32_t icp_compact;        /* 1 (default) or 0.  With 1 (filter modes SIVF and
+                                   RELAXED), objects that compare moving centroids
+                                   only sum into a tile of just the moving centroids:
+                                   dense head rows compacted to them, list fronts
+                                   with compacted positions.  Same results and
+                                   mult-add counts; more device memory (a second
+                                   copy of the head rows, 2 bytes per posting). */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */

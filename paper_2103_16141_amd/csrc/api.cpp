@@ -216,10 +216,12 @@ sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
     dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
     dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
     dev_free(ctx, f->v64, (size_t)f->pcap * 8, &f->bytes);
+    dev_free(ctx, f->cidc, (size_t)f->pcap * 2, &f->bytes);
     f->cid = nullptr;
     f->v32 = nullptr;
     f->v16 = nullptr;
     f->v64 = nullptr;
+    f->cidc = nullptr;
     f->pcap = 0;
     int64_t c = std::max<int64_t>(P + P / 8 + 8, 64);
     STCHK(dev_alloc(ctx, (void**)&f->cid, (size_t)c * 2, &f->bytes));
@@ -229,6 +231,7 @@ sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
         STCHK(dev_alloc(ctx, (void**)&f->v32, (size_t)c * 4, &f->bytes));
     }
     STCHK(dev_alloc(ctx, (void**)&f->v64, (size_t)c * 8, &f->bytes));
+    if (f->comp) STCHK(dev_alloc(ctx, (void**)&f->cidc, (size_t)c * 2, &f->bytes));
     f->pcap = c;
     return SIVF_OK;
 }
@@ -246,6 +249,11 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     dev_free(ctx, f->seg, (size_t)(f->d * f->T + 1) * 8, &f->bytes);
     dev_free(ctx, f->mid, (size_t)(f->d * f->T) * 4, &f->bytes);
     dev_free(ctx, f->rec, (size_t)(f->d * f->T) * 16, &f->bytes);
+    dev_free(ctx, f->mv_ids, (size_t)f->T * f->kt * 2, &f->bytes);
+    dev_free(ctx, f->mv_inv, (size_t)f->T * f->kt * 2, &f->bytes);
+    dev_free(ctx, f->mv_cnt, (size_t)f->T * 4, &f->bytes);
+    dev_free(ctx, f->cidc, (size_t)f->pcap * 2, &f->bytes);
+    dev_free(ctx, f->hcv, (size_t)f->hcap * f->T * head_ktp(f->kt) * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
     dev_free(ctx, f->cid, (size_t)f->pcap * 2, &f->bytes);
     dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
     dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
@@ -273,6 +281,13 @@ sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->seg, (size_t)(d * f->T + 1) * 8, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mid, (size_t)(d * f->T) * 4, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->rec, (size_t)(d * f->T) * 16, &f->bytes);
+    f->comp = ctx->opt.icp_compact &&
+              (ctx->opt.filter_mode == SIVF_MODE_SIVF || ctx->opt.filter_mode == SIVF_MODE_RELAXED);
+    if (f->comp) {
+        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mv_ids, (size_t)f->T * f->kt * 2, &f->bytes);
+        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mv_inv, (size_t)f->T * f->kt * 2, &f->bytes);
+        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mv_cnt, (size_t)f->T * 4, &f->bytes);
+    }
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->lam, (size_t)k, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->cnorm, (size_t)k * 8, &f->bytes);
     if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->head, (size_t)d * 4, &f->bytes);
@@ -333,10 +348,13 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
             if (H > f->hcap) {
                 HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
                 dev_free(ctx, f->hval, (size_t)(f->hcap * kpad * esz), &f->bytes);
+                dev_free(ctx, f->hcv, (size_t)(f->hcap * kpad * esz), &f->bytes);
                 f->hval = nullptr;
+                f->hcv = nullptr;
                 f->hcap = 0;
                 const int64_t c = std::min<int64_t>(H + H / 8 + 16, kHeadCapBytes / (kpad * esz));
                 STCHK(dev_alloc(ctx, &f->hval, (size_t)(c * kpad * esz), &f->bytes));
+                if (f->comp) STCHK(dev_alloc(ctx, &f->hcv, (size_t)(c * kpad * esz), &f->bytes));
                 f->hcap = c;
             }
             HIPCHK(ctx, head_fill(f->cur, f->k, f->head, kpad, f->kt, head_ktp(f->kt), H, f->pdt == SIVF_BF16, f->hval,
@@ -346,6 +364,10 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
         }
     }
     HIPCHK(ctx, seg_records(f->seg, f->mid, f->H > 0 ? f->head : nullptr, f->d, f->T, f->rec, ctx->stream));
+    if (f->comp)
+        HIPCHK(ctx, icp_compact_build(f->lam, f->k, f->kt, f->T, f->d, f->seg, f->mid, f->cid, f->H,
+                                      (int64_t)f->T * head_ktp(f->kt), head_ktp(f->kt), f->pdt == SIVF_BF16, f->hval,
+                                      f->mv_ids, f->mv_inv, f->mv_cnt, f->cidc, f->hcv, ctx->stream));
     if (!f->nonneg) HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
     return SIVF_OK;
 }
@@ -365,6 +387,7 @@ sivf_status sivf_default_options(sivf_options* opt) {
     opt->head_density = 0.5f;
     opt->tiles_per_launch = 0;
     opt->icp_head_moving = 0.25f;
+    opt->icp_compact = 1;
     return SIVF_OK;
 }
 
@@ -380,6 +403,7 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
     if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
     if (!(o.icp_head_moving >= 0.0f && o.icp_head_moving <= 2.0f)) return SIVF_E_INVALID;
+    if (o.icp_compact != 0 && o.icp_compact != 1) return SIVF_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
     sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
@@ -602,6 +626,11 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.mid = f->mid;
     A.rec = f->rec;
     A.d = f->d;
+    A.comp = f->comp;
+    A.mv_ids = f->mv_ids;
+    A.mv_cnt = f->mv_cnt;
+    A.cidc = f->cidc;
+    A.hcv = f->hcv;
     A.cid = f->cid;
     A.pval = f->pdt == SIVF_BF16 ? (const void*)f->v16 : (const void*)f->v32;
     A.lam = f->lam;

@@ -53,6 +53,12 @@ struct WalkArgs {
     const uint4* rec;       // [T*d] record of segment (t, tile) at tile*d + t: start (lo, hi),
                             // length | moving length << 16, dense head row or -1
     int64_t d;
+    // compacted tiles for objects in the ICP branch (comp = 0: not built)
+    int comp;
+    const uint16_t* mv_ids;  // [T*kt] tile-local id of moving centroid c of a tile
+    const int32_t* mv_cnt;   // [T] moving centroids per tile
+    const uint16_t* cidc;    // [P] compacted position of each front (moving) posting
+    const void* hcv;         // head rows compacted to the moving centroids (layout of hval)
     const uint16_t* cid;    // tile-local centroid ids
     const void* pval;       // f32 or bf16 posting values
     const uint8_t* lam;     // flags the file is structured by (lambda^[r-1])
@@ -109,6 +115,13 @@ struct sivf_ivf {
     int64_t* seg = nullptr;         // [d*T + 1]
     int32_t* mid = nullptr;         // [d*T]
     uint4* rec = nullptr;           // [T*d] tile-major segment records read by the walk
+    // compacted tiles for the ICP branch (built when the filter mode uses ICP)
+    int comp = 0;
+    uint16_t* mv_ids = nullptr;     // [T*kt]
+    uint16_t* mv_inv = nullptr;     // [T*kt]
+    int32_t* mv_cnt = nullptr;      // [T]
+    uint16_t* cidc = nullptr;       // [pcap]
+    void* hcv = nullptr;            // [hcap * kpad] in the posting dtype
     uint16_t* cid = nullptr;        // [pcap]
     float* v32 = nullptr;           // [pcap] (posting dtype f32)
     uint16_t* v16 = nullptr;        // [pcap] (posting dtype bf16)
@@ -185,6 +198,10 @@ hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T,
                     IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s);
 // dense head rows: flag[t] = 1 if term t's lists hold >= min_len postings
 hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s);
+hipError_t icp_compact_build(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, int64_t d, const int64_t* seg,
+                             const int32_t* mid, const uint16_t* cid, int64_t H, int64_t kpad, int32_t ktp, int pdt_bf16,
+                             const void* hval, uint16_t* mv_ids, uint16_t* inv, int32_t* mv_cnt, uint16_t* cidc,
+                             void* hcv, hipStream_t s);
 hipError_t seg_records(const int64_t* seg, const int32_t* mid, const int32_t* head, int64_t d, int32_t T, uint4* rec,
                        hipStream_t s);
 hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s);

@@ -201,6 +201,18 @@ __device__ inline void dense_unit32(float* sim, u32x4 w, int c0, float xv) {
     *q = o;
 }
 
+// BF16 rows in a compacted tile with at most 256 moving centroids: a lane's
+// values for positions 4l .. 4l+3 are the first 8 bytes of its 16-byte group
+__device__ inline u32x2 dense_load16h(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
+    return __builtin_amdgcn_raw_buffer_load_b64(dd, lane * 16, (int)(uint32_t)(at * 2), 0);
+}
+
+// FP32 rows in a compacted tile (fewer moving centroids than a batch): 256
+// slots per batch, one 16-byte load per lane (slots 4l .. 4l+3)
+__device__ inline u32x4 dense_load32h(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
+    return __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, (int)(uint32_t)(at * 4), 0);
+}
+
 // sim[ub + c] += xv * row[ub + c] for the batch's centroids below kt
 __device__ inline void dense_accumulate32(float* sim, const DBatch& b, int ub, int kt, float xv, int lane) {
     const int c0 = ub + 4 * lane, c1 = ub + 256 + 4 * lane;
@@ -304,6 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     int32_t* tt = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap)) + wid * kTermCap;
     float* tv = lds + kWalkWaves * (kts + 2 * kCandCap + kTermCap) + wid * kTermCap;
     const __amdgpu_buffer_rsrc_t dd = span_rsrc(A.hval, A.hbytes);
+    const __amdgpu_buffer_rsrc_t ddc = span_rsrc(A.hcv, A.hcv ? A.hbytes : 0);
 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
@@ -378,6 +391,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
             }
             const bool filt = icp || rel;   // compare moving centroids only
             const bool front_only = filt && !CB;
+            // such objects sum into a tile of just the moving centroids in
+            // tiles where few centroids move (elsewhere they read whole head
+            // rows, and a compacted copy as large as them would only crowd
+            // the cache)
+            const bool comp_obj = __builtin_amdgcn_readfirstlane((!CB && A.comp && filt) ? 1 : 0) != 0;
             const bool test_flag = icp && CB;
 
             // Stage the object's first kTermCap terms and values in LDS once
@@ -422,7 +440,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const int tile = tb + pi / nch;
                 const int ch = pi - (tile - tb) * nch;
                 const int32_t base = tile * A.kt;
-                const int32_t width = min(A.kt, A.k - base);
+                const bool comp =
+                    comp_obj && __builtin_amdgcn_readfirstlane(A.icp_head ? (int)A.icp_head[tile] : 0) == 0;
+                const __amdgpu_buffer_rsrc_t dsel = comp ? ddc : dd;
+                // comp: positions 0..m-1 are the tile's moving centroids in ascending id
+                const int32_t width = comp ? A.mv_cnt[tile] : min(A.kt, A.k - base);
+                const int32_t dlim = comp ? width : A.kt;   // dense batches cover [0, dlim)
+                const uint16_t* mvt = A.mv_ids + (int64_t)tile * A.kt;
                 const uint4 rr = nrec;
                 const bool in = nin;
                 const float v = nv;
@@ -445,11 +469,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 // ascending term order, 512 centroids per batch, next batch in
                 // flight while the current one is accumulated
                 int hrow = -1;
-                const bool use_head = A.head && (!filt || (!CB && A.icp_head[tile]));
+                const bool use_head = A.head && (!filt || (comp ? width > 0 : !CB && A.icp_head[tile]));
                 if (use_head && h < n) hrow = hr;
                 unsigned long long dl = ballot(hrow >= 0);
                 const int64_t hb = (int64_t)tile * ktp;   // the tile's slots in a head row
-                if (dl && BF16) {
+                if (dl && BF16 && comp && dlim <= 256) {
+                    // compacted tile of at most 256: one 8-byte load per lane and
+                    // term, two terms per read-add-write, the next pair in flight
+                    float pa = 0.0f, pb = 0.0f;
+                    int64_t ra = 0, rz = 0;
+                    auto take = [&]() -> bool {
+                        if (!dl) return false;
+                        int q = __builtin_ctzll(dl);
+                        dl &= dl - 1;
+                        pa = bcast_f32(v, q);
+                        ra = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        pb = 0.0f;
+                        rz = ra;
+                        if (dl) {
+                            q = __builtin_ctzll(dl);
+                            dl &= dl - 1;
+                            pb = bcast_f32(v, q);
+                            rz = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        }
+                        return true;
+                    };
+                    const int c0 = 4 * lane;
+                    const bool cin = c0 < A.kt;
+                    take();
+                    u32x2 Xa = dense_load16h(dsel, ra, lane), Xb = dense_load16h(dsel, rz, lane), Ya, Yb;
+                    float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
+                    for (;;) {
+                        if (!take()) {
+                            if (cin) dense_unit16x2(sim, Xa.x, Xa.y, Xb.x, Xb.y, c0, xa, xb);
+                            break;
+                        }
+                        Ya = dense_load16h(dsel, ra, lane);
+                        Yb = dense_load16h(dsel, rz, lane);
+                        ya = pa;
+                        yb = pb;
+                        if (cin) dense_unit16x2(sim, Xa.x, Xa.y, Xb.x, Xb.y, c0, xa, xb);
+                        if (!take()) {
+                            if (cin) dense_unit16x2(sim, Ya.x, Ya.y, Yb.x, Yb.y, c0, ya, yb);
+                            break;
+                        }
+                        Xa = dense_load16h(dsel, ra, lane);
+                        Xb = dense_load16h(dsel, rz, lane);
+                        xa = pa;
+                        xb = pb;
+                        if (cin) dense_unit16x2(sim, Ya.x, Ya.y, Yb.x, Yb.y, c0, ya, yb);
+                    }
+                } else if (dl && BF16) {
                     // two terms per pass over the tile (a lone last term is paired
                     // with its own row at weight 0, which adds +-0 exactly)
                     float pa = 0.0f, pb = 0.0f;
@@ -474,11 +544,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                     int ub = 0;
                     auto padv = [&]() -> bool {
                         ub += 512;
-                        if (ub < A.kt) return true;
+                        if (ub < dlim) return true;
                         ub = 0;
                         return take();
                     };
-                    u32x4 Xa = dense_load16(dd, ra + ub, lane), Xb = dense_load16(dd, rz + ub, lane), Ya, Yb;
+                    u32x4 Xa = dense_load16(dsel, ra + ub, lane), Xb = dense_load16(dsel, rz + ub, lane), Ya, Yb;
                     int xu = ub, yu = 0;
                     float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
                     for (;;) {
@@ -486,8 +556,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
                             break;
                         }
-                        Ya = dense_load16(dd, ra + ub, lane);
-                        Yb = dense_load16(dd, rz + ub, lane);
+                        Ya = dense_load16(dsel, ra + ub, lane);
+                        Yb = dense_load16(dsel, rz + ub, lane);
                         yu = ub;
                         ya = pa;
                         yb = pb;
@@ -496,12 +566,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
                             break;
                         }
-                        Xa = dense_load16(dd, ra + ub, lane);
-                        Xb = dense_load16(dd, rz + ub, lane);
+                        Xa = dense_load16(dsel, ra + ub, lane);
+                        Xb = dense_load16(dsel, rz + ub, lane);
                         xu = ub;
                         xa = pa;
                         xb = pb;
                         dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
+                    }
+                } else if (dl && comp) {
+                    // FP32, compacted tile: 256-slot batches, next one in flight
+                    int q = __builtin_ctzll(dl);
+                    dl &= dl - 1;
+                    int ub = 0;
+                    float xv = bcast_f32(v, q);
+                    int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                    auto hadv = [&]() -> bool {
+                        ub += 256;
+                        if (ub < dlim) return true;
+                        if (!dl) return false;
+                        q = __builtin_ctzll(dl);
+                        dl &= dl - 1;
+                        ub = 0;
+                        xv = bcast_f32(v, q);
+                        rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        return true;
+                    };
+                    u32x4 X = dense_load32h(dsel, rb + ub, lane), Y;
+                    int xu = ub, yu = 0;
+                    float xx = xv, yx = 0.0f;
+                    for (;;) {
+                        if (!hadv()) {
+                            if (xu + 4 * lane < A.kt) dense_unit32(sim, X, xu + 4 * lane, xx);
+                            break;
+                        }
+                        Y = dense_load32h(dsel, rb + ub, lane);
+                        yu = ub;
+                        yx = xv;
+                        if (xu + 4 * lane < A.kt) dense_unit32(sim, X, xu + 4 * lane, xx);
+                        if (!hadv()) {
+                            if (yu + 4 * lane < A.kt) dense_unit32(sim, Y, yu + 4 * lane, yx);
+                            break;
+                        }
+                        X = dense_load32h(dsel, rb + ub, lane);
+                        xu = ub;
+                        xx = xv;
+                        if (yu + 4 * lane < A.kt) dense_unit32(sim, Y, yu + 4 * lane, yx);
                     }
                 } else if (dl) {
                     int q = __builtin_ctzll(dl);
@@ -511,7 +620,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                     int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
                     auto dadv = [&]() -> bool {
                         ub += 512;
-                        if (ub < A.kt) return true;
+                        if (ub < dlim) return true;
                         if (!dl) return false;
                         q = __builtin_ctzll(dl);
                         dl &= dl - 1;
@@ -520,7 +629,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
                         return true;
                     };
-                    DBatch X = dense_load32(dd, rb + ub, lane), Y;
+                    DBatch X = dense_load32(dsel, rb + ub, lane), Y;
                     int xu = ub, yu = 0;
                     float xx = xv, yx = 0.0f;
                     for (;;) {
@@ -528,7 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate32(sim, X, xu, A.kt, xx, lane);
                             break;
                         }
-                        Y = dense_load32(dd, rb + ub, lane);
+                        Y = dense_load32(dsel, rb + ub, lane);
                         yu = ub;
                         yx = xv;
                         dense_accumulate32(sim, X, xu, A.kt, xx, lane);
@@ -536,7 +645,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
                             break;
                         }
-                        X = dense_load32(dd, rb + ub, lane);
+                        X = dense_load32(dsel, rb + ub, lane);
                         xu = ub;
                         xx = xv;
                         dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
@@ -563,7 +672,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         // extent rounded up to whole groups of 8 (the arrays keep
                         // 8 spare entries past the last posting)
                         const int64_t span = (hi + 7) & ~7;
-                        dc = span_rsrc(A.cid + b0, span * 2);
+                        dc = span_rsrc((comp ? A.cidc : A.cid) + b0, span * 2);
                         dv = BF16 ? span_rsrc((const uint16_t*)A.pval + b0, span * 2)
                                   : span_rsrc((const float*)A.pval + b0, span * 4);
                         return true;
@@ -607,23 +716,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         float rmax = -INFINITY;
                         int32_t rj = 0x7fffffff;
                         for (int jj = lane; jj < width; jj += 64) {
-                            const int32_t j = base + jj;
+                            // comp: every position is moving; keep the position
+                            // (ascending with the id) and map the winner below
+                            const int32_t j = comp ? jj : base + jj;
                             const float r = sim[jj];
-                            if ((!filt || A.lam[j] == 0) && r > rmax) {
+                            if ((comp || !filt || A.lam[j] == 0) && r > rmax) {
                                 rmax = r;
                                 rj = j;
                             }
                         }
                         double rm = (double)rmax;
                         wave_argmax(rm, rj);
+                        if (comp && rj != 0x7fffffff) rj = base + mvt[rj];
                         if (rj != 0x7fffffff) {
                             tmax = rm - bound_of(A, bd, rm, rj);
                             tj = rj;
                         }
                     } else {
                         for (int jj = lane; jj < width; jj += 64) {
-                            const int32_t j = base + jj;
-                            const bool elig = !filt || A.lam[j] == 0;
+                            const int32_t j = comp ? base + mvt[jj] : base + jj;
+                            const bool elig = comp || !filt || A.lam[j] == 0;
                             if (elig) {
                                 const double r = (double)sim[jj];
                                 const double lo = r - bound_of(A, bd, r, j);
@@ -674,20 +786,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         const int jj = jj0 + lane;
                         bool take = false;
                         float r32 = 0.0f;
+                        int32_t jc = 0;   // the centroid id, once needed
                         if (jj < width) {
-                            const int32_t j = base + jj;
                             r32 = sim[jj];
                             sim[jj] = 0.0f;
-                            if (r32 >= rlow && (!filt || A.lam[j] == 0)) {
+                            if (r32 >= rlow && (comp || !filt || A.lam[base + jj] == 0)) {
+                                jc = comp ? base + mvt[jj] : base + jj;
                                 const double r = (double)r32;
-                                take = r + bound_of(A, bd, r, j) >= theta;
+                                take = r + bound_of(A, bd, r, jc) >= theta;
                             }
                         }
                         const unsigned long long tm = ballot(take);
                         if (tm && !overflow) {
                             const int pos = ccount + lanes_below(tm);
                             if (take && pos < kCandCap) {
-                                cj[pos] = base + jj;
+                                cj[pos] = jc;
                                 cr[pos] = r32;
                             }
                             ccount += __popcll(tm);

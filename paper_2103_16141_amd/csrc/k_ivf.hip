@@ -160,14 +160,16 @@ hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T,
 // 512-centroid block so that one 16-byte load gives a lane both of its
 // 4-centroid groups: slots 8l..8l+3 hold centroids 4l..4l+3 of the block,
 // slots 8l+4..8l+7 centroids 256+4l..256+4l+3.
+// Slot of position c (0 <= c < ktp) inside a tile's part of a row.
+__device__ inline int32_t tile_slot(int32_t c, bool bf16) {
+    if (!bf16) return c;
+    const int32_t i = c & 511;
+    return (c & ~511) + 8 * ((i & 255) >> 2) + 4 * (i >> 8) + (i & 3);
+}
+
 __device__ inline int64_t head_slot(int32_t j, int32_t kt, int32_t ktp, bool bf16) {
     const int32_t tile = j / kt, jj = j - tile * kt;
-    int32_t at = jj;
-    if (bf16) {
-        const int32_t i = jj & 511;
-        at = (jj & ~511) + 8 * ((i & 255) >> 2) + 4 * (i >> 8) + (i & 3);
-    }
-    return (int64_t)tile * ktp + at;
+    return (int64_t)tile * ktp + tile_slot(jj, bf16);
 }
 __global__ void k_head_flags(const int64_t* __restrict__ seg, int64_t d, int32_t T, int64_t min_len,
                              int64_t* __restrict__ flag) {
@@ -287,6 +289,102 @@ hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpa
     hipLaunchKernelGGL(k_head_scatter, dim3((unsigned)blocks), dim3(256), 0, s, st, k, head, kpad, kt, ktp,
                        pdt_bf16 ? nullptr : (float*)hval, pdt_bf16 ? (uint16_t*)hval : nullptr);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- compacted tiles for the ICP branch
+// Objects in the ICP branch compare moving centroids only.  Per tile, the
+// moving centroids (flag 0) in ascending id get compacted positions 0..m-1:
+// mv_ids[tile*kt + c] is the tile-local id at position c, inv[tile*kt + jj]
+// the position of moving centroid jj (0xffff for invariant ones), mv_cnt[tile]
+// = m.  The front (moving) part of every list segment also gets its postings'
+// compacted positions (cidc), and each dense head row a compacted copy over
+// the moving centroids (same padded, interleaved layout), so such an object
+// sums into a tile of m slots with no ids to decode for its head terms.
+__global__ __launch_bounds__(64) void k_mv_tiles(const uint8_t* __restrict__ lam, int32_t k, int32_t kt, int32_t T,
+                                                uint16_t* __restrict__ mv_ids, uint16_t* __restrict__ inv,
+                                                int32_t* __restrict__ mv_cnt) {
+    const int lane = threadIdx.x;
+    for (int32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+        const int32_t b = tile * kt, w = min(kt, k - b);
+        int32_t pos = 0;
+        for (int32_t c0 = 0; c0 < w; c0 += 64) {
+            const int32_t c = c0 + lane;
+            const bool mv = c < w && lam[b + c] == 0;
+            const unsigned long long m = ballot(mv);
+            const int32_t r = pos + lanes_below(m);
+            if (mv) {
+                mv_ids[(int64_t)tile * kt + r] = (uint16_t)c;
+                inv[(int64_t)tile * kt + c] = (uint16_t)r;
+            } else if (c < w) {
+                inv[(int64_t)tile * kt + c] = 0xffffu;
+            }
+            pos += __popcll(m);
+        }
+        if (lane == 0) mv_cnt[tile] = pos;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cidc_fill(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid,
+                                                   const uint16_t* __restrict__ cid, const uint16_t* __restrict__ inv,
+                                                   int64_t d, int32_t T, int32_t kt, uint16_t* __restrict__ cidc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t sidx = wave; sidx < d * T; sidx += nw) {
+        const int64_t tile = sidx % T;
+        const int64_t s = seg[sidx], m = mid[sidx];
+        for (int64_t p = lane; p < m; p += 64) cidc[s + p] = inv[tile * kt + cid[s + p]];
+    }
+}
+
+__global__ void k_head_compact(const uint32_t* __restrict__ h32, const uint16_t* __restrict__ h16,
+                               uint32_t* __restrict__ c32, uint16_t* __restrict__ c16, int64_t H, int64_t kpad,
+                               int32_t kt, int32_t ktp, int32_t T, const uint16_t* __restrict__ mv_ids,
+                               const int32_t* __restrict__ mv_cnt) {
+    const bool bf16 = h16 != nullptr;
+    const int64_t per_row = (int64_t)T * ktp, n = H * per_row;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        const int64_t r = idx / per_row, rem = idx - r * per_row;
+        const int32_t tile = (int32_t)(rem / ktp), c = (int32_t)(rem - (int64_t)tile * ktp);
+        const int64_t base = r * kpad + (int64_t)tile * ktp;
+        const int64_t dst = base + tile_slot(c, bf16);
+        if (c < mv_cnt[tile]) {
+            const int64_t src = base + tile_slot(mv_ids[(int64_t)tile * kt + c], bf16);
+            if (bf16) c16[dst] = h16[src];
+            else c32[dst] = h32[src];
+        } else {
+            if (bf16) c16[dst] = 0;
+            else c32[dst] = 0u;
+        }
+    }
+}
+
+hipError_t icp_compact_build(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, int64_t d, const int64_t* seg,
+                             const int32_t* mid, const uint16_t* cid, int64_t H, int64_t kpad, int32_t ktp, int pdt_bf16,
+                             const void* hval, uint16_t* mv_ids, uint16_t* inv, int32_t* mv_cnt, uint16_t* cidc,
+                             void* hcv, hipStream_t s) {
+    hipLaunchKernelGGL(k_mv_tiles, dim3((unsigned)std::min<int32_t>(T, 4096)), dim3(64), 0, s, lam, k, kt, T, mv_ids,
+                       inv, mv_cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nseg = d * T;
+    if (nseg > 0) {
+        const int64_t blocks = std::min<int64_t>((nseg * 64 + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_cidc_fill, dim3((unsigned)blocks), dim3(256), 0, s, seg, mid, cid, inv, d, T, kt, cidc);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t n = H * T * (int64_t)ktp;
+    if (n > 0) {
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_head_compact, dim3((unsigned)blocks), dim3(256), 0, s,
+                           pdt_bf16 ? nullptr : (const uint32_t*)hval, pdt_bf16 ? (const uint16_t*)hval : nullptr,
+                           pdt_bf16 ? nullptr : (uint32_t*)hcv, pdt_bf16 ? (uint16_t*)hcv : nullptr, H, kpad, kt, ktp,
+                           T, mv_ids, mv_cnt);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 // ---------------------------------------------------------------- export to the paper's layout
