@@ -118,20 +118,24 @@ typedef struct {
                                    tile 1, ... so one tile's lists stay cache-
                                    resident; a value >= the tile count walks every
                                    tile of an object in one launch.  Same results. */
-    float icp_head_moving;      /* in [0, 2]; default 0.25.  Objects in the ICP branch
-                                   read the dense head rows (all centroids; the
-                                   invariant ones are not eligible for them) in tiles
-                                   where at least this fraction of the centroids is
-                                   moving, else the moving part of the lists; > 1
-                                   never.  Same results and mult-add counts.
-                                   (Used when icp_compact is 0.) */
-    int32_t icp_compact;        /* 1 (default) or 0.  With 1 (filter modes SIVF and
-                                   RELAXED), objects that compare moving centroids
-                                   only sum into a tile of just the moving centroids:
-                                   dense head rows compacted to them, list fronts
-                                   with compacted positions.  Same results and
-                                   mult-add counts; more device memory (a second
-                                   copy of the head rows, 2 bytes per posting). */
+    float icp_head_moving;      /* < 0 (default): automatic, 0.25 with FP32 postings and
+                                   0.55 with BF16; else in [0, 2].  A tile is
+                                   "mostly moving" when at least this fraction of its
+                                   centroids moves.  Objects in the ICP branch read the
+                                   dense head rows (all centroids; the invariant ones
+                                   are not eligible for them) in mostly-moving tiles;
+                                   elsewhere they sum into a compacted tile of the
+                                   moving centroids (icp_compact 1) or walk the moving
+                                   part of the lists (icp_compact 0); > 1 never counts
+                                   a tile as mostly moving.  Same results and mult-add
+                                   counts. */
+    int32_t icp_compact;        /* 1 (default) or 0; see icp_head_moving.  With 1
+                                   (filter modes SIVF and RELAXED) the compacted tiles
+                                   use dense head rows compacted to the moving
+                                   centroids and list fronts with compacted positions:
+                                   same results and mult-add counts, more device memory
+                                   (a second copy of the head rows, 2 bytes per
+                                   posting). */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */
