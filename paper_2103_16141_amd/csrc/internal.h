@@ -85,7 +85,8 @@ struct WalkArgs {
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)
     const int32_t* head;    // [d] row of each term, -1 if none
-    const uint8_t* icp_head;  // [T] 1: objects in the ICP branch read head rows in this tile too
+    const uint8_t* icp_head;  // [T] 1: a mostly-moving tile (objects in the ICP branch read the
+                              // whole head rows there; elsewhere a compacted tile, if comp)
     const void* hval;       // [H * kpad] values in the posting dtype
     int64_t kpad;           // row length: T * head_ktp(kt) (each tile padded to 512 slots)
     int64_t hbytes;         // bytes of hval (< 2^32)
@@ -128,7 +129,7 @@ struct sivf_ivf {
     double* v64 = nullptr;          // [pcap] FP64 values (exact re-score over whole lists)
     int64_t P = 0, pcap = 0;
     int32_t* head = nullptr;        // [d] dense head row of each term, -1 if none
-    uint8_t* icp_head = nullptr;    // [T] 1: objects in the ICP branch read head rows in this tile
+    uint8_t* icp_head = nullptr;    // [T] 1: mostly-moving tile (see WalkArgs::icp_head)
     void* hval = nullptr;           // [hcap * kpad] dense head rows, posting dtype
     int64_t H = 0, hcap = 0;        // head rows in use / allocated
     uint8_t* lam = nullptr;         // [k]

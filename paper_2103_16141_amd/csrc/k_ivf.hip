@@ -210,8 +210,9 @@ __global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ 
 }
 
 // icp_ok[tile] = 1 when at least min_moving of the tile's centroids are moving
-// (flag 0): objects in the ICP branch then read head rows there too (the
-// invariant centroids' partial sums are never eligible for them).
+// (flag 0): objects in the ICP branch then read the whole head rows there (the
+// invariant centroids' partial sums are never eligible for them); in the other
+// tiles they sum into the compacted tile of the moving centroids.
 __global__ void k_head_icp_tiles(const uint8_t* __restrict__ lam, int32_t k, int32_t kt, int32_t T, float min_moving,
                                  uint8_t* __restrict__ icp_ok) {
     __shared__ int cnt;
