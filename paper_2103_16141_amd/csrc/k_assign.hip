@@ -1,16 +1,21 @@
-// Assignment step (Alg. 4) on CDNA: a wave takes one object, stages its
-// terms in LDS, and for each centroid tile walks the posting lists of the
-// object's terms, gather-accumulating v * u into a per-wave similarity tile
-// in LDS.  Centroid ids are unique inside a list, so the lanes of one
-// instruction never collide: the tile is updated with plain LDS
-// read-add-write (a wave's LDS operations complete in order; LDS float
-// atomics are ~25x slower on gfx950), and the accumulation order is fixed:
-// term-major, ascending term.  Postings are fetched 256 at a time through
-// per-list buffer descriptors, with the next batch's loads in flight while
-// the current one is accumulated; this keeps the scalar and vector
-// instruction count per posting low, which is what bounds the walk.  An
-// object whose own cluster was invariant (ICP branch) stops each list at the
-// moving/invariant boundary of the structured file.
+// Assignment step (Alg. 4) on CDNA.  One launch per centroid tile covers all
+// objects (per-object state carries over between launches); a wave takes one
+// object at a time, stages its terms in LDS, reads one 16-byte record per
+// (term, tile) -- the segment bounds in the structured file, the length of its
+// moving part, the term's dense head row if any -- and gather-accumulates
+// v * u into a per-wave similarity tile in LDS:
+//   * head terms (held by most centroids) from dense rows of values, 512
+//     centroids per batch with 16-byte loads and 16-byte LDS read-add-writes;
+//   * other terms from their list segment, 256 postings per batch through a
+//     per-list buffer descriptor, the next batch's loads in flight.
+// Centroid ids are unique inside a list, so the lanes of one instruction never
+// collide: the tile is updated with plain LDS read-add-write (a wave's LDS
+// operations complete in order; LDS float atomics are ~25x slower on gfx950).
+// An object whose own cluster was invariant (ICP branch) compares moving
+// centroids only: it stops each list at the moving/invariant boundary, and in
+// tiles where few centroids move it sums into a tile of just those (head rows
+// and list fronts compacted to them).  The loads of head rows and postings go
+// through the vector memory data path, which is what bounds the walk.
 //
 // Exactness: the FP32 pass gives rho_hat with |rho_hat - rho_fp64| <= B per
 // centroid (rounding of posting values, of object values, of the FP32 fold
