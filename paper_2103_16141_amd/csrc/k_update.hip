@@ -5,12 +5,15 @@
 //    blocks, and an in-block bitonic sort of (cluster, local id) keys that
 //    gives each object its rank among same-cluster objects of its block.  The
 //    result lists every cluster's members in ascending object id.
-// 2. One wave per cluster (persistent waves, each with a private dense FP64
-//    row W of length d in HBM): w_t = sum of member values in ascending
-//    object id (sequential per term, exactly the reference fold), then in
-//    ascending term order q_t = w_t / |C_j|, s = s + q_t*q_t (sequential),
-//    support = {t : q_t != 0}; u_t = q_t / sqrt(s).  W is cleared as it is
-//    read, so it is zero again for the next cluster.
+// 2. One wave per cluster (persistent waves, each with private dense FP64
+//    sums: term ids below kHotTerms in LDS, the rest in a row W of length d
+//    in HBM): w_t = sum of member values in ascending object id (sequential
+//    per term, exactly the reference fold), then in ascending term order
+//    q_t = w_t / |C_j|, s = s + q_t*q_t (sequential), support
+//    = {t : q_t != 0}; u_t = q_t / sqrt(s).  The sums are cleared as they are
+//    read, so they are zero again for the next cluster.  The member chain is
+//    the cost: each member ends with a wait for its stores, so every load is
+//    issued unconditionally and ahead of its use (see member_sums).
 //    Clusters with no members, or with unchanged members (flag 1), keep their
 //    previous centroid bitwise (it would be recomputed to the same bits).
 #include "internal.h"
