@@ -237,10 +237,6 @@ def main():
     ap.add_argument("--tiles-per-launch", type=int, default=None,
                     help="centroid tiles per walk launch (default: library's, one tile per launch)")
     ap.add_argument("--skip-soft", action="store_true", help="skip the differentiation-form timing")
-    ap.add_argument("--icp-head-moving", type=float, default=None,
-                    help="ICP objects read head rows in tiles with at least this moving fraction (default: library's)")
-    ap.add_argument("--icp-compact", type=int, default=None, choices=(0, 1),
-                    help="objects comparing moving centroids only sum into a tile of the moving centroids (1, default)")
     ap.add_argument("--filter", default="sivf", choices=["sivf", "ivf", "cbicp", "relaxed"],
                     help="ICP realisation: structured file (SIVF), none (IVF), per-posting test (IVF-CBICP), "
                          "SIVF with relaxed ICP")
@@ -278,16 +274,14 @@ def main():
     k = w["k"]
 
     ctx32 = Context(0, posting_dtype="fp32", k_tile=args.k_tile, head_density=args.head_density,
-                    tiles_per_launch=args.tiles_per_launch, filter_mode=args.filter,
-                    icp_head_moving=args.icp_head_moving, icp_compact=args.icp_compact)
+                    tiles_per_launch=args.tiles_per_launch, filter_mode=args.filter)
     st32, wall32, sizes, a32 = run_lloyd_timed(ctx32, X, k, ids, args.steps, args.warmup, "fp32")
     s32 = summarize(st32, wall32, sizes, corpus.nnz, corpus.n, "fp32")
     ctx32.close()
     out_bf16 = None
     if not args.skip_bf16:
         ctx16 = Context(0, posting_dtype="bf16", k_tile=args.k_tile, head_density=args.head_density,
-                    tiles_per_launch=args.tiles_per_launch, filter_mode=args.filter,
-                    icp_head_moving=args.icp_head_moving, icp_compact=args.icp_compact)
+                    tiles_per_launch=args.tiles_per_launch, filter_mode=args.filter)
         st16, wall16, sizes16, a16 = run_lloyd_timed(ctx16, X, k, ids, args.steps, args.warmup, "bf16")
         s16 = summarize(st16, wall16, sizes16, corpus.nnz, corpus.n, "bf16")
         ctx16.close()

@@ -110,32 +110,16 @@ typedef struct {
     float head_density;         /* in [0, 1]; default 0.5.  Terms held by at least this
                                    fraction of the k centroids also get a dense row of
                                    posting values (zeros for absent centroids) that the
-                                   walk reads for objects outside the ICP branch; 0
-                                   disables.  Same results and mult-add counts either
+                                   walk reads instead of the term's lists (objects in
+                                   the ICP branch of modes SIVF and RELAXED read only
+                                   the moving centroids' part; in CBICP they walk the
+                                   lists); 0 disables.  Same results and mult-add counts either
                                    way (a memory layout choice, not the paper's). */
     int32_t tiles_per_launch;   /* centroid tiles the walk covers per kernel launch;
                                    0 (default) = 1: all objects walk tile 0, then
                                    tile 1, ... so one tile's lists stay cache-
                                    resident; a value >= the tile count walks every
                                    tile of an object in one launch.  Same results. */
-    float icp_head_moving;      /* < 0 (default): automatic, 0.25 with FP32 postings and
-                                   0.55 with BF16; else in [0, 2].  A tile is
-                                   "mostly moving" when at least this fraction of its
-                                   centroids moves.  Objects in the ICP branch read the
-                                   dense head rows (all centroids; the invariant ones
-                                   are not eligible for them) in mostly-moving tiles;
-                                   elsewhere they sum into a compacted tile of the
-                                   moving centroids (icp_compact 1) or walk the moving
-                                   part of the lists (icp_compact 0); > 1 never counts
-                                   a tile as mostly moving.  Same results and mult-add
-                                   counts. */
-    int32_t icp_compact;        /* 1 (default) or 0; see icp_head_moving.  With 1
-                                   (filter modes SIVF and RELAXED) the compacted tiles
-                                   use dense head rows compacted to the moving
-                                   centroids and list fronts with compacted positions:
-                                   same results and mult-add counts, more device memory
-                                   (a second copy of the head rows, 2 bytes per
-                                   posting). */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */

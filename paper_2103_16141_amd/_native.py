@@ -23,8 +23,7 @@ class sivf_csr(ctypes.Structure):
 class sivf_options(ctypes.Structure):
     _fields_ = [("posting_dtype", ctypes.c_int), ("filter_mode", ctypes.c_int32), ("k_tile", ctypes.c_int32),
                 ("certify", ctypes.c_int32), ("workspace_cap_bytes", ctypes.c_size_t),
-                ("head_density", ctypes.c_float), ("tiles_per_launch", ctypes.c_int32),
-                ("icp_head_moving", ctypes.c_float), ("icp_compact", ctypes.c_int32)]
+                ("head_density", ctypes.c_float), ("tiles_per_launch", ctypes.c_int32)]
 
 
 class sivf_iter_stats(ctypes.Structure):

@@ -115,8 +115,7 @@ class Ivf:
 
 class Context:
     def __init__(self, device=0, posting_dtype="fp32", filter_mode="sivf", k_tile=0, certify=True,
-                 workspace_cap_bytes=0, stream=None, head_density=None, tiles_per_launch=None,
-                 icp_head_moving=None, icp_compact=None):
+                 workspace_cap_bytes=0, stream=None, head_density=None, tiles_per_launch=None):
         lib = N.load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         idx = self.device.index if self.device.index is not None else 0
@@ -132,10 +131,6 @@ class Context:
             opt.head_density = float(head_density)
         if tiles_per_launch is not None:
             opt.tiles_per_launch = int(tiles_per_launch)
-        if icp_head_moving is not None:
-            opt.icp_head_moving = float(icp_head_moving)
-        if icp_compact is not None:
-            opt.icp_compact = 1 if icp_compact else 0
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

@@ -216,12 +216,10 @@ sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
     dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
     dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
     dev_free(ctx, f->v64, (size_t)f->pcap * 8, &f->bytes);
-    dev_free(ctx, f->cidc, (size_t)f->pcap * 2, &f->bytes);
     f->cid = nullptr;
     f->v32 = nullptr;
     f->v16 = nullptr;
     f->v64 = nullptr;
-    f->cidc = nullptr;
     f->pcap = 0;
     int64_t c = std::max<int64_t>(P + P / 8 + 8, 64);
     STCHK(dev_alloc(ctx, (void**)&f->cid, (size_t)c * 2, &f->bytes));
@@ -231,7 +229,6 @@ sivf_status postings_reserve(sivf_ctx* ctx, sivf_ivf* f, int64_t P) {
         STCHK(dev_alloc(ctx, (void**)&f->v32, (size_t)c * 4, &f->bytes));
     }
     STCHK(dev_alloc(ctx, (void**)&f->v64, (size_t)c * 8, &f->bytes));
-    if (f->comp) STCHK(dev_alloc(ctx, (void**)&f->cidc, (size_t)c * 2, &f->bytes));
     f->pcap = c;
     return SIVF_OK;
 }
@@ -249,11 +246,8 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     dev_free(ctx, f->seg, (size_t)(f->d * f->T + 1) * 8, &f->bytes);
     dev_free(ctx, f->mid, (size_t)(f->d * f->T) * 4, &f->bytes);
     dev_free(ctx, f->rec, (size_t)(f->d * f->T) * 16, &f->bytes);
-    dev_free(ctx, f->mv_ids, (size_t)f->T * f->kt * 2, &f->bytes);
-    dev_free(ctx, f->mv_inv, (size_t)f->T * f->kt * 2, &f->bytes);
-    dev_free(ctx, f->mv_cnt, (size_t)f->T * 4, &f->bytes);
-    dev_free(ctx, f->cidc, (size_t)f->pcap * 2, &f->bytes);
-    dev_free(ctx, f->hcv, (size_t)f->hcap * f->T * head_ktp(f->kt) * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
+    dev_free(ctx, f->perm, (size_t)f->k * 4, &f->bytes);
+    dev_free(ctx, f->iperm, (size_t)f->k * 4, &f->bytes);
     dev_free(ctx, f->cid, (size_t)f->pcap * 2, &f->bytes);
     dev_free(ctx, f->v32, (size_t)f->pcap * 4, &f->bytes);
     dev_free(ctx, f->v16, (size_t)f->pcap * 2, &f->bytes);
@@ -261,7 +255,6 @@ void free_file(sivf_ctx* ctx, sivf_ivf* f) {
     dev_free(ctx, f->lam, (size_t)f->k, &f->bytes);
     dev_free(ctx, f->cnorm, (size_t)f->k * 8, &f->bytes);
     dev_free(ctx, f->head, (size_t)f->d * 4, &f->bytes);
-    dev_free(ctx, f->icp_head, (size_t)f->T, &f->bytes);
     dev_free(ctx, f->hval, (size_t)f->hcap * f->T * head_ktp(f->kt) * (f->pdt == SIVF_BF16 ? 2 : 4), &f->bytes);
     delete f;
 }
@@ -281,17 +274,11 @@ sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->seg, (size_t)(d * f->T + 1) * 8, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mid, (size_t)(d * f->T) * 4, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->rec, (size_t)(d * f->T) * 16, &f->bytes);
-    f->comp = ctx->opt.icp_compact &&
-              (ctx->opt.filter_mode == SIVF_MODE_SIVF || ctx->opt.filter_mode == SIVF_MODE_RELAXED);
-    if (f->comp) {
-        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mv_ids, (size_t)f->T * f->kt * 2, &f->bytes);
-        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mv_inv, (size_t)f->T * f->kt * 2, &f->bytes);
-        if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->mv_cnt, (size_t)f->T * 4, &f->bytes);
-    }
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->perm, (size_t)k * 4, &f->bytes);
+    if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->iperm, (size_t)k * 4, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->lam, (size_t)k, &f->bytes);
     if (st == SIVF_OK) st = dev_alloc(ctx, (void**)&f->cnorm, (size_t)k * 8, &f->bytes);
     if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->head, (size_t)d * 4, &f->bytes);
-    if (st == SIVF_OK && ctx->opt.head_density > 0.0f) st = dev_alloc(ctx, (void**)&f->icp_head, (size_t)f->T, &f->bytes);
     if (st != SIVF_OK) {
         free_file(ctx, f);
         return st;
@@ -300,7 +287,8 @@ sivf_status new_file(sivf_ctx* ctx, int32_t k, int64_t d, sivf_ivf** out) {
     return SIVF_OK;
 }
 
-// Structure f's current centroids by the flags in f->lam (Alg. 5 second half).
+// Structure f's current centroids by the flags in f->lam (Alg. 5 second half):
+// positions put the moving centroids first, then the file is built by position.
 sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
     const int64_t W64 = ivf_w64(f->k);
     const int64_t nseg2 = f->d * f->T * 2;
@@ -313,7 +301,16 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
     STCHK(ws(ctx, "ivf_off", nseg2 + 1, &w.off));
     STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(std::max<int64_t>(nseg2, f->k + 1), ctx->vx_n + 1)) + 8,
              &w.scan_ws));
-    HIPCHK(ctx, ivf_count(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, ctx->stream));
+    int64_t* pmv = nullptr;
+    int64_t* pmvpre = nullptr;
+    STCHK(ws(ctx, "ivf_mv", (int64_t)f->k, &pmv));
+    STCHK(ws(ctx, "ivf_mvpre", (int64_t)f->k + 1, &pmvpre));
+    HIPCHK(ctx, ivf_perm(f->lam, f->k, pmv, pmvpre, w.scan_ws, f->perm, f->iperm, ctx->stream));
+    int64_t nmv = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nmv, pmvpre + f->k, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    f->nmv = (int32_t)nmv;
+    HIPCHK(ctx, ivf_count(f->cur, f->k, f->d, f->kt, f->T, f->iperm, f->nmv, w, ctx->stream));
     HIPCHK(ctx, ivf_offsets(f->d, f->T, w, f->seg, f->mid, ctx->stream));
     // dense head rows: terms whose lists hold >= ceil(head_density * k) postings
     int64_t* hflag = nullptr;
@@ -339,7 +336,8 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
         return fail(ctx, SIVF_E_HIP, "internal: %lld postings for %lld centroid entries", (long long)P, (long long)total);
     STCHK(postings_reserve(ctx, f, P));
     f->P = P;
-    HIPCHK(ctx, ivf_fill(f->cur, f->k, f->d, f->kt, f->T, f->lam, w, f->cid, f->v32, f->v16, f->v64, ctx->stream));
+    HIPCHK(ctx, ivf_fill(f->cur, f->k, f->d, f->kt, f->T, f->iperm, f->nmv, w, f->cid, f->v32, f->v16, f->v64,
+                         ctx->stream));
     f->H = 0;
     if (f->head) {
         const int64_t kpad = (int64_t)f->T * head_ktp(f->kt), esz = f->pdt == SIVF_BF16 ? 2 : 4;
@@ -348,30 +346,18 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
             if (H > f->hcap) {
                 HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
                 dev_free(ctx, f->hval, (size_t)(f->hcap * kpad * esz), &f->bytes);
-                dev_free(ctx, f->hcv, (size_t)(f->hcap * kpad * esz), &f->bytes);
                 f->hval = nullptr;
-                f->hcv = nullptr;
                 f->hcap = 0;
                 const int64_t c = std::min<int64_t>(H + H / 8 + 16, kHeadCapBytes / (kpad * esz));
                 STCHK(dev_alloc(ctx, &f->hval, (size_t)(c * kpad * esz), &f->bytes));
-                if (f->comp) STCHK(dev_alloc(ctx, &f->hcv, (size_t)(c * kpad * esz), &f->bytes));
                 f->hcap = c;
             }
-            HIPCHK(ctx, head_fill(f->cur, f->k, f->head, kpad, f->kt, head_ktp(f->kt), H, f->pdt == SIVF_BF16, f->hval,
-                                  ctx->stream));
-            // automatic: measured best over 30 iterations at N=8M, k=10k (BF16 rows
-            // are half the bytes, so compacted tiles pay off at higher fractions)
-            const float ihm = ctx->opt.icp_head_moving >= 0.0f ? ctx->opt.icp_head_moving
-                                                               : (f->pdt == SIVF_BF16 ? 0.55f : 0.25f);
-            HIPCHK(ctx, head_icp_tiles(f->lam, f->k, f->kt, f->T, ihm, f->icp_head, ctx->stream));
+            HIPCHK(ctx, head_fill(f->cur, f->k, f->head, f->iperm, kpad, f->kt, head_ktp(f->kt), H,
+                                  f->pdt == SIVF_BF16, f->hval, ctx->stream));
             f->H = H;
         }
     }
     HIPCHK(ctx, seg_records(f->seg, f->mid, f->H > 0 ? f->head : nullptr, f->d, f->T, f->rec, ctx->stream));
-    if (f->comp)
-        HIPCHK(ctx, icp_compact_build(f->lam, f->k, f->kt, f->T, f->d, f->seg, f->mid, f->cid, f->H,
-                                      (int64_t)f->T * head_ktp(f->kt), head_ktp(f->kt), f->pdt == SIVF_BF16, f->hval,
-                                      f->mv_ids, f->mv_inv, f->mv_cnt, f->cidc, f->hcv, ctx->stream));
     if (!f->nonneg) HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
     return SIVF_OK;
 }
@@ -390,8 +376,6 @@ sivf_status sivf_default_options(sivf_options* opt) {
     opt->workspace_cap_bytes = 0;
     opt->head_density = 0.5f;
     opt->tiles_per_launch = 0;
-    opt->icp_head_moving = -1.0f;
-    opt->icp_compact = 1;
     return SIVF_OK;
 }
 
@@ -406,8 +390,6 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
     if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
     if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
-    if (!(o.icp_head_moving < 0.0f || o.icp_head_moving <= 2.0f)) return SIVF_E_INVALID;
-    if (o.icp_compact != 0 && o.icp_compact != 1) return SIVF_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
     sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
@@ -630,11 +612,8 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.mid = f->mid;
     A.rec = f->rec;
     A.d = f->d;
-    A.comp = f->comp;
-    A.mv_ids = f->mv_ids;
-    A.mv_cnt = f->mv_cnt;
-    A.cidc = f->cidc;
-    A.hcv = f->hcv;
+    A.perm = f->perm;
+    A.nmv = f->nmv;
     A.cid = f->cid;
     A.pval = f->pdt == SIVF_BF16 ? (const void*)f->v16 : (const void*)f->v32;
     A.lam = f->lam;
@@ -680,7 +659,6 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
         if (launches > 1) STCHK(ws(ctx, "st_rel", m, &A.st_rel));
     }
     A.head = f->H > 0 ? f->head : nullptr;
-    A.icp_head = f->icp_head;
     A.hval = f->hval;
     A.kpad = (int64_t)f->T * head_ktp(f->kt);
     A.hbytes = f->H * A.kpad * (f->pdt == SIVF_BF16 ? 2 : 4);

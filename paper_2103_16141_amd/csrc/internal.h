@@ -53,13 +53,9 @@ struct WalkArgs {
     const uint4* rec;       // [T*d] record of segment (t, tile) at tile*d + t: start (lo, hi),
                             // length | moving length << 16, dense head row or -1
     int64_t d;
-    // compacted tiles for objects in the ICP branch (comp = 0: not built)
-    int comp;
-    const uint16_t* mv_ids;  // [T*kt] tile-local id of moving centroid c of a tile
-    const int32_t* mv_cnt;   // [T] moving centroids per tile
-    const uint16_t* cidc;    // [P] compacted position of each front (moving) posting
-    const void* hcv;         // head rows compacted to the moving centroids (layout of hval)
-    const uint16_t* cid;    // tile-local centroid ids
+    const uint16_t* cid;    // tile-local positions
+    const int32_t* perm;    // [k] centroid id at each position
+    int32_t nmv;            // moving centroids: positions [0, nmv)
     const void* pval;       // f32 or bf16 posting values
     const uint8_t* lam;     // flags the file is structured by (lambda^[r-1])
     const double* cnorm;    // ||mu_j|| upper bounds (signed-data bound)
@@ -85,8 +81,6 @@ struct WalkArgs {
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)
     const int32_t* head;    // [d] row of each term, -1 if none
-    const uint8_t* icp_head;  // [T] 1: a mostly-moving tile (objects in the ICP branch read the
-                              // whole head rows there; elsewhere a compacted tile, if comp)
     const void* hval;       // [H * kpad] values in the posting dtype
     int64_t kpad;           // row length: T * head_ktp(kt) (each tile padded to 512 slots)
     int64_t hbytes;         // bytes of hval (< 2^32)
@@ -116,20 +110,15 @@ struct sivf_ivf {
     int64_t* seg = nullptr;         // [d*T + 1]
     int32_t* mid = nullptr;         // [d*T]
     uint4* rec = nullptr;           // [T*d] tile-major segment records read by the walk
-    // compacted tiles for the ICP branch (built when the filter mode uses ICP)
-    int comp = 0;
-    uint16_t* mv_ids = nullptr;     // [T*kt]
-    uint16_t* mv_inv = nullptr;     // [T*kt]
-    int32_t* mv_cnt = nullptr;      // [T]
-    uint16_t* cidc = nullptr;       // [pcap]
-    void* hcv = nullptr;            // [hcap * kpad] in the posting dtype
-    uint16_t* cid = nullptr;        // [pcap]
+    int32_t* perm = nullptr;        // [k] centroid id at each position (moving first)
+    int32_t* iperm = nullptr;       // [k] position of each centroid
+    int32_t nmv = 0;                // moving centroids in the current structure
+    uint16_t* cid = nullptr;        // [pcap] position minus tile*kt
     float* v32 = nullptr;           // [pcap] (posting dtype f32)
     uint16_t* v16 = nullptr;        // [pcap] (posting dtype bf16)
     double* v64 = nullptr;          // [pcap] FP64 values (exact re-score over whole lists)
     int64_t P = 0, pcap = 0;
     int32_t* head = nullptr;        // [d] dense head row of each term, -1 if none
-    uint8_t* icp_head = nullptr;    // [T] 1: mostly-moving tile (see WalkArgs::icp_head)
     void* hval = nullptr;           // [hcap * kpad] dense head rows, posting dtype
     int64_t H = 0, hcap = 0;        // head rows in use / allocated
     uint8_t* lam = nullptr;         // [k]
@@ -192,26 +181,25 @@ struct IvfBuildWs {
     int64_t* scan_ws;
 };
 int64_t ivf_w64(int32_t k);
-hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam,
-                     IvfBuildWs w, hipStream_t s);
+// positions: moving centroids (flag 0) first, each group in ascending id;
+// mvpre[k] = number of moving centroids
+hipError_t ivf_perm(const uint8_t* lam, int32_t k, int64_t* mv, int64_t* mvpre, int64_t* scan_ws, int32_t* perm,
+                    int32_t* iperm, hipStream_t s);
+hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const int32_t* iperm,
+                     int32_t n_moving, IvfBuildWs w, hipStream_t s);
 hipError_t ivf_offsets(int64_t d, int32_t T, IvfBuildWs w, int64_t* seg, int32_t* mid, hipStream_t s);
-hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam,
-                    IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s);
+hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const int32_t* iperm,
+                    int32_t n_moving, IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64,
+                    hipStream_t s);
 // dense head rows: flag[t] = 1 if term t's lists hold >= min_len postings
 hipError_t head_flags(const int64_t* seg, int64_t d, int32_t T, int64_t min_len, int64_t* flag, hipStream_t s);
-hipError_t icp_compact_build(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, int64_t d, const int64_t* seg,
-                             const int32_t* mid, const uint16_t* cid, int64_t H, int64_t kpad, int32_t ktp, int pdt_bf16,
-                             const void* hval, uint16_t* mv_ids, uint16_t* inv, int32_t* mv_cnt, uint16_t* cidc,
-                             void* hcv, hipStream_t s);
 hipError_t seg_records(const int64_t* seg, const int32_t* mid, const int32_t* head, int64_t d, int32_t T, uint4* rec,
                        hipStream_t s);
 hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32_t* head, hipStream_t s);
-hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, float min_moving, uint8_t* icp_ok,
-                          hipStream_t s);
 // head-row slots per tile: kt rounded up to whole 512-centroid batches
 inline int32_t head_ktp(int32_t kt) { return (kt + 511) & ~511; }
-hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int32_t kt, int32_t ktp, int64_t H,
-                     int pdt_bf16, void* hval, hipStream_t s);
+hipError_t head_fill(const Store st, int32_t k, const int32_t* head, const int32_t* iperm, int64_t kpad, int32_t kt,
+                     int32_t ktp, int64_t H, int pdt_bf16, void* hval, hipStream_t s);
 hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val,
                       int64_t* ws_counts, int64_t* scan_ws, hipStream_t s);
 hipError_t store_export(const Store st, int32_t k, const int64_t* c_ptr, int32_t* c_col, double* c_val,

@@ -11,11 +11,13 @@
 // Centroid ids are unique inside a list, so the lanes of one instruction never
 // collide: the tile is updated with plain LDS read-add-write (a wave's LDS
 // operations complete in order; LDS float atomics are ~25x slower on gfx950).
-// An object whose own cluster was invariant (ICP branch) compares moving
-// centroids only: it stops each list at the moving/invariant boundary, and in
-// tiles where few centroids move it sums into a tile of just those (head rows
-// and list fronts compacted to them).  The loads of head rows and postings go
-// through the vector memory data path, which is what bounds the walk.
+// Tiles and lists are laid out by position, the moving centroids first (the
+// file keeps perm: position -> centroid id).  An object whose own cluster was
+// invariant (ICP branch) compares moving centroids only: it stops each list
+// at the moving/invariant boundary, reads only the moving prefix of the head
+// rows, and skips the tiles past the last moving centroid.  The loads of head
+// rows and postings go through the vector memory data path, which is what
+// bounds the walk.
 //
 // Exactness: the FP32 pass gives rho_hat with |rho_hat - rho_fp64| <= B per
 // centroid (rounding of posting values, of object values, of the FP32 fold
@@ -160,7 +162,7 @@ __device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Bat
     if (CB && test_flag) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if ((int)c[i] < A.kt && A.lam[base + c[i]]) pr[i] = 0.0f;
+            if ((int)c[i] < A.kt && base + (int)c[i] >= A.nmv) pr[i] = 0.0f;
     }
     const float o0 = sim[c[0]], o1 = sim[c[1]], o2 = sim[c[2]], o3 = sim[c[3]];
     sim[c[0]] = o0 + pr[0];
@@ -204,18 +206,6 @@ __device__ inline void dense_unit32(float* sim, u32x4 w, int c0, float xv) {
     o.z = o.z + xv * __uint_as_float(w.z);
     o.w = o.w + xv * __uint_as_float(w.w);
     *q = o;
-}
-
-// BF16 rows in a compacted tile with at most 256 moving centroids: a lane's
-// values for positions 4l .. 4l+3 are the first 8 bytes of its 16-byte group
-__device__ inline u32x2 dense_load16h(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
-    return __builtin_amdgcn_raw_buffer_load_b64(dd, lane * 16, (int)(uint32_t)(at * 2), 0);
-}
-
-// FP32 rows in a compacted tile (fewer moving centroids than a batch): 256
-// slots per batch, one 16-byte load per lane (slots 4l .. 4l+3)
-__device__ inline u32x4 dense_load32h(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
-    return __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, (int)(uint32_t)(at * 4), 0);
 }
 
 // sim[ub + c] += xv * row[ub + c] for the batch's centroids below kt
@@ -321,7 +311,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     int32_t* tt = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap)) + wid * kTermCap;
     float* tv = lds + kWalkWaves * (kts + 2 * kCandCap + kTermCap) + wid * kTermCap;
     const __amdgpu_buffer_rsrc_t dd = span_rsrc(A.hval, A.hbytes);
-    const __amdgpu_buffer_rsrc_t ddc = span_rsrc(A.hcv, A.hcv ? A.hbytes : 0);
 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
@@ -341,6 +330,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 own_old = A.own_prev[i];
             }
             if (tb == 0) icp_cnt += icp ? 1 : 0;
+            // relaxed ICP: own cluster moved, but the exact similarity to the
+            // own centroid did not decrease -> moving centroids only
+            bool rel = false;
+            if (A.relaxed && A.icp_on && !icp) {
+                if (tb == 0) {
+                    const double rn = exact_rho(A, A.st, r0, n, a_old);
+                    rel = rn >= A.own64_prev[i];
+                    if (lane == 0) {
+                        A.own64_cur[i] = rn;
+                        if (te < A.T) A.st_rel[i] = rel ? 1 : 0;
+                    }
+                    rel_cnt += rel ? 1 : 0;
+                } else {
+                    rel = A.st_rel[i] != 0;
+                }
+            }
+            const bool filt = icp || rel;   // compare moving centroids only
+            const bool front_only = filt && !CB;
+            const bool test_flag = icp && CB;
+            // front_only objects stop at the tile holding the last moving
+            // position; in a launch wholly past it their state stays as is
+            const int tmv = (A.nmv + A.kt - 1) / A.kt;
+            const int te_obj = front_only ? max(tb, min(te, tmv)) : te;
+            if (te_obj == tb && tb > 0 && te < A.T) continue;
             double xnorm = 0.0;
             if (!A.nonneg) {
                 double ss = 0.0;
@@ -351,7 +364,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 xnorm = sqrt(wave_sum_f64(ss)) * (1.0 + 0x1p-40);
             }
             const Bound bd = bound_setup(A, n, xnorm);
-
             double theta = -INFINITY;   // largest lower bound so far
             double best_lo = -INFINITY;
             int32_t best_j = 0x7fffffff;
@@ -378,30 +390,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 ccount = 1;
             }
             bool overflow = ccount > kCandCap;
-            // relaxed ICP: own cluster moved, but the exact similarity to the
-            // own centroid did not decrease -> moving centroids only
-            bool rel = false;
-            if (A.relaxed && A.icp_on && !icp) {
-                if (tb == 0) {
-                    const double rn = exact_rho(A, A.st, r0, n, a_old);
-                    rel = rn >= A.own64_prev[i];
-                    if (lane == 0) {
-                        A.own64_cur[i] = rn;
-                        if (te < A.T) A.st_rel[i] = rel ? 1 : 0;
-                    }
-                    rel_cnt += rel ? 1 : 0;
-                } else {
-                    rel = A.st_rel[i] != 0;
-                }
-            }
-            const bool filt = icp || rel;   // compare moving centroids only
-            const bool front_only = filt && !CB;
-            // such objects sum into a tile of just the moving centroids in
-            // tiles where few centroids move (elsewhere they read whole head
-            // rows, and a compacted copy as large as them would only crowd
-            // the cache)
-            const bool comp_obj = __builtin_amdgcn_readfirstlane((!CB && A.comp && filt) ? 1 : 0) != 0;
-            const bool test_flag = icp && CB;
 
             // Stage the object's first kTermCap terms and values in LDS once
             // (each lane later reads only the entries it wrote itself).
@@ -413,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
             const int nch = max(1, (n + 63) >> 6);
-            const int npairs = (te - tb) * nch;
+            const int npairs = (te_obj - tb) * nch;
             // segment record and object value of pair pi, issued one pair ahead
             // of their use and decoded only there: every lane loads (terms past
             // the row read term 0's record), so no condition makes the compiler
@@ -445,13 +433,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const int tile = tb + pi / nch;
                 const int ch = pi - (tile - tb) * nch;
                 const int32_t base = tile * A.kt;
-                const bool comp =
-                    comp_obj && __builtin_amdgcn_readfirstlane(A.icp_head ? (int)A.icp_head[tile] : 0) == 0;
-                const __amdgpu_buffer_rsrc_t dsel = comp ? ddc : dd;
-                // comp: positions 0..m-1 are the tile's moving centroids in ascending id
-                const int32_t width = comp ? A.mv_cnt[tile] : min(A.kt, A.k - base);
-                const int32_t dlim = comp ? width : A.kt;   // dense batches cover [0, dlim)
-                const uint16_t* mvt = A.mv_ids + (int64_t)tile * A.kt;
+                const int32_t width = min(A.kt, A.k - base);
+                // eligible prefix of the tile (moving positions for filt objects)
+                const int32_t elim = filt ? min(width, max(0, A.nmv - base)) : width;
+                // dense batches cover [0, dlim); the tile range the walk may
+                // have touched, and the epilogue clears, is [0, ew)
+                const int32_t dlim = front_only ? elim : A.kt;
+                const int32_t ew = front_only ? min(width, (elim + 511) & ~511) : width;
                 const uint4 rr = nrec;
                 const bool in = nin;
                 const float v = nv;
@@ -469,62 +457,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 // buffer descriptors made per list: the lane offset is a
                 // constant, the batch offset is scalar, and lanes past the
                 // list's end read 0 from the hardware range check.
-                // ---- head terms: dense rows (in the ICP branch only in tiles
-                // where most centroids move; the rest cannot win there), in
-                // ascending term order, 512 centroids per batch, next batch in
-                // flight while the current one is accumulated
+                // ---- head terms: dense rows (in the ICP branch their moving
+                // prefix only), in ascending term order, 512 centroids per
+                // batch, next batch in flight while the current one is
+                // accumulated
                 int hrow = -1;
-                const bool use_head = A.head && (!filt || (comp ? width > 0 : !CB && A.icp_head[tile]));
+                const bool use_head = A.head && !(filt && CB);
                 if (use_head && h < n) hrow = hr;
                 unsigned long long dl = ballot(hrow >= 0);
                 const int64_t hb = (int64_t)tile * ktp;   // the tile's slots in a head row
-                if (dl && BF16 && comp && dlim <= 256) {
-                    // compacted tile of at most 256: one 8-byte load per lane and
-                    // term, two terms per read-add-write, the next pair in flight
-                    float pa = 0.0f, pb = 0.0f;
-                    int64_t ra = 0, rz = 0;
-                    auto take = [&]() -> bool {
-                        if (!dl) return false;
-                        int q = __builtin_ctzll(dl);
-                        dl &= dl - 1;
-                        pa = bcast_f32(v, q);
-                        ra = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
-                        pb = 0.0f;
-                        rz = ra;
-                        if (dl) {
-                            q = __builtin_ctzll(dl);
-                            dl &= dl - 1;
-                            pb = bcast_f32(v, q);
-                            rz = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
-                        }
-                        return true;
-                    };
-                    const int c0 = 4 * lane;
-                    const bool cin = c0 < A.kt;
-                    take();
-                    u32x2 Xa = dense_load16h(dsel, ra, lane), Xb = dense_load16h(dsel, rz, lane), Ya, Yb;
-                    float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
-                    for (;;) {
-                        if (!take()) {
-                            if (cin) dense_unit16x2(sim, Xa.x, Xa.y, Xb.x, Xb.y, c0, xa, xb);
-                            break;
-                        }
-                        Ya = dense_load16h(dsel, ra, lane);
-                        Yb = dense_load16h(dsel, rz, lane);
-                        ya = pa;
-                        yb = pb;
-                        if (cin) dense_unit16x2(sim, Xa.x, Xa.y, Xb.x, Xb.y, c0, xa, xb);
-                        if (!take()) {
-                            if (cin) dense_unit16x2(sim, Ya.x, Ya.y, Yb.x, Yb.y, c0, ya, yb);
-                            break;
-                        }
-                        Xa = dense_load16h(dsel, ra, lane);
-                        Xb = dense_load16h(dsel, rz, lane);
-                        xa = pa;
-                        xb = pb;
-                        if (cin) dense_unit16x2(sim, Ya.x, Ya.y, Yb.x, Yb.y, c0, ya, yb);
-                    }
-                } else if (dl && BF16) {
+                if (dl && BF16) {
                     // two terms per pass over the tile (a lone last term is paired
                     // with its own row at weight 0, which adds +-0 exactly)
                     float pa = 0.0f, pb = 0.0f;
@@ -553,7 +495,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         ub = 0;
                         return take();
                     };
-                    u32x4 Xa = dense_load16(dsel, ra + ub, lane), Xb = dense_load16(dsel, rz + ub, lane), Ya, Yb;
+                    u32x4 Xa = dense_load16(dd, ra + ub, lane), Xb = dense_load16(dd, rz + ub, lane), Ya, Yb;
                     int xu = ub, yu = 0;
                     float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
                     for (;;) {
@@ -561,8 +503,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
                             break;
                         }
-                        Ya = dense_load16(dsel, ra + ub, lane);
-                        Yb = dense_load16(dsel, rz + ub, lane);
+                        Ya = dense_load16(dd, ra + ub, lane);
+                        Yb = dense_load16(dd, rz + ub, lane);
                         yu = ub;
                         ya = pa;
                         yb = pb;
@@ -571,51 +513,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
                             break;
                         }
-                        Xa = dense_load16(dsel, ra + ub, lane);
-                        Xb = dense_load16(dsel, rz + ub, lane);
+                        Xa = dense_load16(dd, ra + ub, lane);
+                        Xb = dense_load16(dd, rz + ub, lane);
                         xu = ub;
                         xa = pa;
                         xb = pb;
                         dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
-                    }
-                } else if (dl && comp) {
-                    // FP32, compacted tile: 256-slot batches, next one in flight
-                    int q = __builtin_ctzll(dl);
-                    dl &= dl - 1;
-                    int ub = 0;
-                    float xv = bcast_f32(v, q);
-                    int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
-                    auto hadv = [&]() -> bool {
-                        ub += 256;
-                        if (ub < dlim) return true;
-                        if (!dl) return false;
-                        q = __builtin_ctzll(dl);
-                        dl &= dl - 1;
-                        ub = 0;
-                        xv = bcast_f32(v, q);
-                        rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
-                        return true;
-                    };
-                    u32x4 X = dense_load32h(dsel, rb + ub, lane), Y;
-                    int xu = ub, yu = 0;
-                    float xx = xv, yx = 0.0f;
-                    for (;;) {
-                        if (!hadv()) {
-                            if (xu + 4 * lane < A.kt) dense_unit32(sim, X, xu + 4 * lane, xx);
-                            break;
-                        }
-                        Y = dense_load32h(dsel, rb + ub, lane);
-                        yu = ub;
-                        yx = xv;
-                        if (xu + 4 * lane < A.kt) dense_unit32(sim, X, xu + 4 * lane, xx);
-                        if (!hadv()) {
-                            if (yu + 4 * lane < A.kt) dense_unit32(sim, Y, yu + 4 * lane, yx);
-                            break;
-                        }
-                        X = dense_load32h(dsel, rb + ub, lane);
-                        xu = ub;
-                        xx = xv;
-                        if (yu + 4 * lane < A.kt) dense_unit32(sim, Y, yu + 4 * lane, yx);
                     }
                 } else if (dl) {
                     int q = __builtin_ctzll(dl);
@@ -634,7 +537,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
                         return true;
                     };
-                    DBatch X = dense_load32(dsel, rb + ub, lane), Y;
+                    DBatch X = dense_load32(dd, rb + ub, lane), Y;
                     int xu = ub, yu = 0;
                     float xx = xv, yx = 0.0f;
                     for (;;) {
@@ -642,7 +545,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate32(sim, X, xu, A.kt, xx, lane);
                             break;
                         }
-                        Y = dense_load32(dsel, rb + ub, lane);
+                        Y = dense_load32(dd, rb + ub, lane);
                         yu = ub;
                         yx = xv;
                         dense_accumulate32(sim, X, xu, A.kt, xx, lane);
@@ -650,7 +553,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
                             break;
                         }
-                        X = dense_load32(dsel, rb + ub, lane);
+                        X = dense_load32(dd, rb + ub, lane);
                         xu = ub;
                         xx = xv;
                         dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
@@ -677,7 +580,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         // extent rounded up to whole groups of 8 (the arrays keep
                         // 8 spare entries past the last posting)
                         const int64_t span = (hi + 7) & ~7;
-                        dc = span_rsrc((comp ? A.cidc : A.cid) + b0, span * 2);
+                        dc = span_rsrc(A.cid + b0, span * 2);
                         dv = BF16 ? span_rsrc((const uint16_t*)A.pval + b0, span * 2)
                                   : span_rsrc((const float*)A.pval + b0, span * 4);
                         return true;
@@ -720,34 +623,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         // lower bound is that of its largest eligible r
                         float rmax = -INFINITY;
                         int32_t rj = 0x7fffffff;
-                        for (int jj = lane; jj < width; jj += 64) {
-                            // comp: every position is moving; keep the position
-                            // (ascending with the id) and map the winner below
-                            const int32_t j = comp ? jj : base + jj;
+                        for (int jj = lane; jj < elim; jj += 64) {
                             const float r = sim[jj];
-                            if ((comp || !filt || A.lam[j] == 0) && r > rmax) {
+                            if (r > rmax) {
                                 rmax = r;
-                                rj = j;
+                                rj = base + jj;
                             }
                         }
                         double rm = (double)rmax;
-                        wave_argmax(rm, rj);
-                        if (comp && rj != 0x7fffffff) rj = base + mvt[rj];
+                        wave_argmax(rm, rj);   // a position; the centroid id below
+                        if (rj != 0x7fffffff) rj = A.perm[rj];
                         if (rj != 0x7fffffff) {
                             tmax = rm - bound_of(A, bd, rm, rj);
                             tj = rj;
                         }
                     } else {
-                        for (int jj = lane; jj < width; jj += 64) {
-                            const int32_t j = comp ? base + mvt[jj] : base + jj;
-                            const bool elig = comp || !filt || A.lam[j] == 0;
-                            if (elig) {
-                                const double r = (double)sim[jj];
-                                const double lo = r - bound_of(A, bd, r, j);
-                                if (lo > tmax) {
-                                    tmax = lo;
-                                    tj = j;
-                                }
+                        for (int jj = lane; jj < elim; jj += 64) {
+                            const int32_t j = A.perm[base + jj];
+                            const double r = (double)sim[jj];
+                            const double lo = r - bound_of(A, bd, r, j);
+                            if (lo > tmax || (lo == tmax && j < tj)) {
+                                tmax = lo;
+                                tj = j;
                             }
                         }
                         wave_argmax(tmax, tj);
@@ -787,16 +684,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                                          ((1.0 + bd.crel + 0x1p-50) * (1.0 + 0x1p-50)) * (1.0 - 0x1p-45);
                         rlow = __double2float_rd(t);
                     }
-                    for (int jj0 = 0; jj0 < width; jj0 += 64) {
+                    for (int jj0 = 0; jj0 < ew; jj0 += 64) {
                         const int jj = jj0 + lane;
                         bool take = false;
                         float r32 = 0.0f;
                         int32_t jc = 0;   // the centroid id, once needed
-                        if (jj < width) {
+                        if (jj < ew) {
                             r32 = sim[jj];
                             sim[jj] = 0.0f;
-                            if (r32 >= rlow && (comp || !filt || A.lam[base + jj] == 0)) {
-                                jc = comp ? base + mvt[jj] : base + jj;
+                            if (r32 >= rlow && jj < elim) {
+                                jc = A.perm[base + jj];
                                 const double r = (double)r32;
                                 take = r + bound_of(A, bd, r, jc) >= theta;
                             }
@@ -1000,10 +897,10 @@ __global__ __launch_bounds__(64) void k_rescore_full(WalkArgs A, const double* _
             double tb = -INFINITY;
             int32_t tj = 0x7fffffff;
             for (int jj = lane; jj < width; jj += 64) {
-                const int32_t j = base + jj;
                 const double r = acc[jj];
                 acc[jj] = 0.0;
-                if (!icp || A.lam[j] == 0) {
+                if (!icp || base + jj < A.nmv) {
+                    const int32_t j = A.perm[base + jj];
                     if (r > tb || (r == tb && j < tj)) {
                         tb = r;
                         tj = j;

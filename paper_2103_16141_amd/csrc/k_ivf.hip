@@ -2,12 +2,18 @@
 // inverted-file structure" and "make structured inverted-file").
 //
 // Device layout (one list per term, split by centroid tile for the LDS-tiled
-// walk): postings are ordered by (term, tile, part, centroid id) where part 0
+// walk): postings are ordered by (term, tile, part, position) where part 0
 // holds the moving centroids (flag 0) and part 1 the invariant ones.  With a
 // single tile this is exactly the paper's per-term [moving | invariant] list.
+// Positions renumber the centroids with the moving ones first, each group in
+// ascending id (perm[q] = centroid at position q, iperm its inverse), and the
+// tiles cover positions: a tile's moving centroids are a prefix of it, so an
+// object that compares moving centroids only reads that prefix and skips the
+// tiles past the last moving centroid.  Inside each part positions ascend
+// with the ids, so per part the order is the paper's.
 //   seg[t*T + tile]  start of segment (t, tile); its end is seg[t*T + tile + 1]
 //   mid[t*T + tile]  length of the moving part of that segment
-//   cid[p]           centroid id minus tile*kt (16 bits)
+//   cid[p]           position minus tile*kt (16 bits)
 //   v32/v16[p]       posting value, RN to f32 (or RNE of that to bf16)
 //   v64[p]           the FP64 value (exact re-score over whole lists)
 //
@@ -25,14 +31,45 @@ namespace sivf {
 
 int64_t ivf_w64(int32_t k) { return ((int64_t)k + 63) / 64; }
 
-__global__ void k_ivf_bits(Store st, int32_t k, int64_t d, unsigned long long* __restrict__ bm) {
+// ---------------------------------------------------------------- positions
+__global__ void k_perm_flags(const uint8_t* __restrict__ lam, int32_t k, int64_t* __restrict__ mv) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j < k) mv[j] = (lam && lam[j]) ? 0 : 1;
+}
+
+// mvpre = exclusive scan of the moving flags; n_moving = mvpre[k]
+__global__ void k_perm_fill(const uint8_t* __restrict__ lam, int32_t k, const int64_t* __restrict__ mvpre,
+                            int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    const int64_t nm = mvpre[k];
+    const int64_t q = (lam && lam[j]) ? nm + (j - mvpre[j]) : mvpre[j];
+    iperm[j] = (int32_t)q;
+    perm[q] = (int32_t)j;
+}
+
+hipError_t ivf_perm(const uint8_t* lam, int32_t k, int64_t* mv, int64_t* mvpre, int64_t* scan_ws, int32_t* perm,
+                    int32_t* iperm, hipStream_t s) {
+    const unsigned blocks = (unsigned)(((int64_t)k + 255) / 256);
+    hipLaunchKernelGGL(k_perm_flags, dim3(blocks), dim3(256), 0, s, lam, k, mv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = exclusive_scan_i64(mv, mvpre, k, scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_perm_fill, dim3(blocks), dim3(256), 0, s, lam, k, mvpre, perm, iperm);
+    return hipGetLastError();
+}
+
+__global__ void k_ivf_bits(Store st, int32_t k, int64_t d, const int32_t* __restrict__ iperm,
+                           unsigned long long* __restrict__ bm) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t j = wave; j < k; j += nw) {
         const int64_t b = st.start[j], m = st.nnz[j];
-        unsigned long long* row = bm + (j >> 6) * d;
-        const unsigned long long bit = 1ull << (j & 63);
+        const int64_t q = iperm[j];
+        unsigned long long* row = bm + (q >> 6) * d;
+        const unsigned long long bit = 1ull << (q & 63);
         for (int64_t p = lane; p < m; p += 64) {
             const int32_t t = st.term[b + p];
             if (t >= 0 && t < d) atomicOr(&row[t], bit);
@@ -40,13 +77,14 @@ __global__ void k_ivf_bits(Store st, int32_t k, int64_t d, unsigned long long* _
     }
 }
 
-__global__ void k_lam_bits(const uint8_t* __restrict__ lam, int32_t k, unsigned long long* __restrict__ lbits) {
+// invariant bits by position: positions n_moving .. k-1
+__global__ void k_lam_bits(int32_t k, int32_t n_moving, unsigned long long* __restrict__ lbits) {
     int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (w >= ((int64_t)k + 63) / 64) return;
     unsigned long long m = 0;
     for (int b = 0; b < 64; ++b) {
-        int64_t j = w * 64 + b;
-        if (j < k && lam && lam[j]) m |= 1ull << b;
+        int64_t q = w * 64 + b;
+        if (q < k && q >= n_moving) m |= 1ull << b;
     }
     lbits[w] = m;
 }
@@ -75,15 +113,15 @@ __global__ void k_ivf_counts(const unsigned long long* __restrict__ bm, const un
     cnt[(t * T + tile) * 2 + 1] = c1;
 }
 
-hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam, IvfBuildWs w,
-                     hipStream_t s) {
+hipError_t ivf_count(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const int32_t* iperm,
+                     int32_t n_moving, IvfBuildWs w, hipStream_t s) {
     const int64_t W64 = ivf_w64(k);
     hipError_t e = fill_u64(w.bm, 0ull, W64 * d, s);
     if (e != hipSuccess) return e;
     int64_t blocks = ((int64_t)k * 64 + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_ivf_bits, dim3((unsigned)blocks), dim3(256), 0, s, st, k, d, w.bm);
-    hipLaunchKernelGGL(k_lam_bits, dim3((unsigned)((W64 + 255) / 256)), dim3(256), 0, s, lam, k, w.lbits);
+    hipLaunchKernelGGL(k_ivf_bits, dim3((unsigned)blocks), dim3(256), 0, s, st, k, d, iperm, w.bm);
+    hipLaunchKernelGGL(k_lam_bits, dim3((unsigned)((W64 + 255) / 256)), dim3(256), 0, s, k, n_moving, w.lbits);
     int64_t nt = d * T;
     hipLaunchKernelGGL(k_ivf_counts, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, w.bm, w.lbits, d, kt, T,
                        W64, w.pre0, w.pre1, w.cnt);
@@ -111,7 +149,8 @@ hipError_t ivf_offsets(int64_t d, int32_t T, IvfBuildWs w, int64_t* seg, int32_t
     return hipGetLastError();
 }
 
-__global__ void k_ivf_fill(Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* __restrict__ lam,
+__global__ void k_ivf_fill(Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const int32_t* __restrict__ iperm,
+                           int32_t n_moving,
                            const unsigned long long* __restrict__ bm, const unsigned long long* __restrict__ lbits,
                            const uint16_t* __restrict__ pre0, const uint16_t* __restrict__ pre1,
                            const int64_t* __restrict__ off, uint16_t* __restrict__ cid, float* __restrict__ v32,
@@ -120,12 +159,13 @@ __global__ void k_ivf_fill(Store st, int32_t k, int64_t d, int32_t kt, int32_t T
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t j = wave; j < k; j += nw) {
-        const int part = (lam && lam[j]) ? 1 : 0;
-        const int64_t tile = j / kt, w = j >> 6;
-        const unsigned long long below = (1ull << (j & 63)) - 1ull;
+        const int64_t q = iperm[j];
+        const int part = q >= n_moving ? 1 : 0;
+        const int64_t tile = q / kt, w = q >> 6;
+        const unsigned long long below = (1ull << (q & 63)) - 1ull;
         const unsigned long long pm = part ? lbits[w] : ~lbits[w];
         const uint16_t* pre = part ? pre1 : pre0;
-        const uint16_t local = (uint16_t)(j - tile * kt);
+        const uint16_t local = (uint16_t)(q - tile * kt);
         const int64_t b = st.start[j], m = st.nnz[j];
         for (int64_t p = lane; p < m; p += 64) {
             const int64_t t = st.term[b + p];
@@ -141,12 +181,13 @@ __global__ void k_ivf_fill(Store st, int32_t k, int64_t d, int32_t kt, int32_t T
     }
 }
 
-hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const uint8_t* lam, IvfBuildWs w,
-                    uint16_t* cid, float* v32, uint16_t* v16, double* v64, hipStream_t s) {
+hipError_t ivf_fill(const Store st, int32_t k, int64_t d, int32_t kt, int32_t T, const int32_t* iperm,
+                    int32_t n_moving, IvfBuildWs w, uint16_t* cid, float* v32, uint16_t* v16, double* v64,
+                    hipStream_t s) {
     int64_t blocks = ((int64_t)k * 64 + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_ivf_fill, dim3((unsigned)blocks), dim3(256), 0, s, st, k, d, kt, T, lam, w.bm, w.lbits,
-                       w.pre0, w.pre1, w.off, cid, v32, v16, v64);
+    hipLaunchKernelGGL(k_ivf_fill, dim3((unsigned)blocks), dim3(256), 0, s, st, k, d, kt, T, iperm, n_moving, w.bm,
+                       w.lbits, w.pre0, w.pre1, w.off, cid, v32, v16, v64);
     return hipGetLastError();
 }
 
@@ -191,8 +232,9 @@ __global__ void k_head_zero(uint32_t* __restrict__ w, int64_t nw) {
 }
 
 // one wave per centroid: scatter its head-term values into the rows
-__global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ head, int64_t kpad, int32_t kt,
-                               int32_t ktp, float* __restrict__ h32, uint16_t* __restrict__ h16) {
+__global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ head, const int32_t* __restrict__ iperm,
+                               int64_t kpad, int32_t kt, int32_t ktp, float* __restrict__ h32,
+                               uint16_t* __restrict__ h16) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -202,38 +244,11 @@ __global__ void k_head_scatter(Store st, int32_t k, const int32_t* __restrict__ 
             const int32_t r = head[st.term[b + p]];
             if (r >= 0) {
                 const float f = (float)st.val[b + p];  // round to nearest even
-                if (h32) h32[r * kpad + head_slot((int32_t)j, kt, ktp, false)] = f;
-                else h16[r * kpad + head_slot((int32_t)j, kt, ktp, true)] = f32_to_bf16_rne(f);
+                if (h32) h32[r * kpad + head_slot(iperm[j], kt, ktp, false)] = f;
+                else h16[r * kpad + head_slot(iperm[j], kt, ktp, true)] = f32_to_bf16_rne(f);
             }
         }
     }
-}
-
-// icp_ok[tile] = 1 when at least min_moving of the tile's centroids are moving
-// (flag 0): objects in the ICP branch then read the whole head rows there (the
-// invariant centroids' partial sums are never eligible for them); in the other
-// tiles they sum into the compacted tile of the moving centroids.
-__global__ void k_head_icp_tiles(const uint8_t* __restrict__ lam, int32_t k, int32_t kt, int32_t T, float min_moving,
-                                 uint8_t* __restrict__ icp_ok) {
-    __shared__ int cnt;
-    for (int32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
-        if (threadIdx.x == 0) cnt = 0;
-        __syncthreads();
-        const int32_t b = tile * kt, w = min(kt, k - b);
-        int mine = 0;
-        for (int32_t c = threadIdx.x; c < w; c += blockDim.x) mine += lam[b + c] ? 0 : 1;
-        atomicAdd(&cnt, mine);
-        __syncthreads();
-        if (threadIdx.x == 0) icp_ok[tile] = (float)cnt >= min_moving * (float)w ? 1 : 0;
-        __syncthreads();
-    }
-}
-
-hipError_t head_icp_tiles(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, float min_moving, uint8_t* icp_ok,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_head_icp_tiles, dim3((unsigned)std::min<int32_t>(T, 4096)), dim3(256), 0, s, lam, k, kt, T,
-                       min_moving, icp_ok);
-    return hipGetLastError();
 }
 
 // Tile-major copy of the segment bounds for the walk: one 16-byte record per
@@ -275,8 +290,8 @@ hipError_t head_index(const int64_t* flag, const int64_t* scan, int64_t d, int32
     return hipGetLastError();
 }
 
-hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpad, int32_t kt, int32_t ktp, int64_t H,
-                     int pdt_bf16, void* hval, hipStream_t s) {
+hipError_t head_fill(const Store st, int32_t k, const int32_t* head, const int32_t* iperm, int64_t kpad, int32_t kt,
+                     int32_t ktp, int64_t H, int pdt_bf16, void* hval, hipStream_t s) {
     const int64_t bytes = H * kpad * (pdt_bf16 ? 2 : 4);
     const int64_t nw = (bytes + 3) / 4;
     if (nw == 0) return hipSuccess;
@@ -287,105 +302,9 @@ hipError_t head_fill(const Store st, int32_t k, const int32_t* head, int64_t kpa
     if (e != hipSuccess) return e;
     int64_t blocks = ((int64_t)k * 64 + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_head_scatter, dim3((unsigned)blocks), dim3(256), 0, s, st, k, head, kpad, kt, ktp,
+    hipLaunchKernelGGL(k_head_scatter, dim3((unsigned)blocks), dim3(256), 0, s, st, k, head, iperm, kpad, kt, ktp,
                        pdt_bf16 ? nullptr : (float*)hval, pdt_bf16 ? (uint16_t*)hval : nullptr);
     return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- compacted tiles for the ICP branch
-// Objects in the ICP branch compare moving centroids only.  Per tile, the
-// moving centroids (flag 0) in ascending id get compacted positions 0..m-1:
-// mv_ids[tile*kt + c] is the tile-local id at position c, inv[tile*kt + jj]
-// the position of moving centroid jj (0xffff for invariant ones), mv_cnt[tile]
-// = m.  The front (moving) part of every list segment also gets its postings'
-// compacted positions (cidc), and each dense head row a compacted copy over
-// the moving centroids (same padded, interleaved layout), so such an object
-// sums into a tile of m slots with no ids to decode for its head terms.
-__global__ __launch_bounds__(64) void k_mv_tiles(const uint8_t* __restrict__ lam, int32_t k, int32_t kt, int32_t T,
-                                                uint16_t* __restrict__ mv_ids, uint16_t* __restrict__ inv,
-                                                int32_t* __restrict__ mv_cnt) {
-    const int lane = threadIdx.x;
-    for (int32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
-        const int32_t b = tile * kt, w = min(kt, k - b);
-        int32_t pos = 0;
-        for (int32_t c0 = 0; c0 < w; c0 += 64) {
-            const int32_t c = c0 + lane;
-            const bool mv = c < w && lam[b + c] == 0;
-            const unsigned long long m = ballot(mv);
-            const int32_t r = pos + lanes_below(m);
-            if (mv) {
-                mv_ids[(int64_t)tile * kt + r] = (uint16_t)c;
-                inv[(int64_t)tile * kt + c] = (uint16_t)r;
-            } else if (c < w) {
-                inv[(int64_t)tile * kt + c] = 0xffffu;
-            }
-            pos += __popcll(m);
-        }
-        if (lane == 0) mv_cnt[tile] = pos;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_cidc_fill(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid,
-                                                   const uint16_t* __restrict__ cid, const uint16_t* __restrict__ inv,
-                                                   int64_t d, int32_t T, int32_t kt, uint16_t* __restrict__ cidc) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t sidx = wave; sidx < d * T; sidx += nw) {
-        const int64_t tile = sidx % T;
-        const int64_t s = seg[sidx], m = mid[sidx];
-        for (int64_t p = lane; p < m; p += 64) cidc[s + p] = inv[tile * kt + cid[s + p]];
-    }
-}
-
-__global__ void k_head_compact(const uint32_t* __restrict__ h32, const uint16_t* __restrict__ h16,
-                               uint32_t* __restrict__ c32, uint16_t* __restrict__ c16, int64_t H, int64_t kpad,
-                               int32_t kt, int32_t ktp, int32_t T, const uint16_t* __restrict__ mv_ids,
-                               const int32_t* __restrict__ mv_cnt) {
-    const bool bf16 = h16 != nullptr;
-    const int64_t per_row = (int64_t)T * ktp, n = H * per_row;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += stride) {
-        const int64_t r = idx / per_row, rem = idx - r * per_row;
-        const int32_t tile = (int32_t)(rem / ktp), c = (int32_t)(rem - (int64_t)tile * ktp);
-        const int64_t base = r * kpad + (int64_t)tile * ktp;
-        const int64_t dst = base + tile_slot(c, bf16);
-        if (c < mv_cnt[tile]) {
-            const int64_t src = base + tile_slot(mv_ids[(int64_t)tile * kt + c], bf16);
-            if (bf16) c16[dst] = h16[src];
-            else c32[dst] = h32[src];
-        } else {
-            if (bf16) c16[dst] = 0;
-            else c32[dst] = 0u;
-        }
-    }
-}
-
-hipError_t icp_compact_build(const uint8_t* lam, int32_t k, int32_t kt, int32_t T, int64_t d, const int64_t* seg,
-                             const int32_t* mid, const uint16_t* cid, int64_t H, int64_t kpad, int32_t ktp, int pdt_bf16,
-                             const void* hval, uint16_t* mv_ids, uint16_t* inv, int32_t* mv_cnt, uint16_t* cidc,
-                             void* hcv, hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_tiles, dim3((unsigned)std::min<int32_t>(T, 4096)), dim3(64), 0, s, lam, k, kt, T, mv_ids,
-                       inv, mv_cnt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t nseg = d * T;
-    if (nseg > 0) {
-        const int64_t blocks = std::min<int64_t>((nseg * 64 + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_cidc_fill, dim3((unsigned)blocks), dim3(256), 0, s, seg, mid, cid, inv, d, T, kt, cidc);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    const int64_t n = H * T * (int64_t)ktp;
-    if (n > 0) {
-        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_head_compact, dim3((unsigned)blocks), dim3(256), 0, s,
-                           pdt_bf16 ? nullptr : (const uint32_t*)hval, pdt_bf16 ? (const uint16_t*)hval : nullptr,
-                           pdt_bf16 ? nullptr : (uint32_t*)hcv, pdt_bf16 ? (uint16_t*)hcv : nullptr, H, kpad, kt, ktp,
-                           T, mv_ids, mv_cnt);
-        e = hipGetLastError();
-    }
-    return e;
 }
 
 // ---------------------------------------------------------------- export to the paper's layout
@@ -401,7 +320,8 @@ __global__ void k_exp_counts(const int64_t* __restrict__ seg, const int32_t* __r
 
 __global__ void k_exp_fill(const int64_t* __restrict__ seg, const int32_t* __restrict__ mid,
                            const uint16_t* __restrict__ cid, const double* __restrict__ v64, int64_t d, int32_t T,
-                           int32_t kt, const int64_t* __restrict__ tptr, int32_t* __restrict__ p_cid,
+                           int32_t kt, const int32_t* __restrict__ perm, const int64_t* __restrict__ tptr,
+                           int32_t* __restrict__ p_cid,
                            double* __restrict__ p_val) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -413,7 +333,7 @@ __global__ void k_exp_fill(const int64_t* __restrict__ seg, const int32_t* __res
                 int64_t s0 = seg[t * T + tile], s1 = seg[t * T + tile + 1], sm = s0 + mid[t * T + tile];
                 int64_t lo = part ? sm : s0, hi = part ? s1 : sm;
                 for (int64_t p = lo + lane; p < hi; p += 64) {
-                    if (p_cid) p_cid[o + (p - lo)] = (int32_t)cid[p] + tile * kt;
+                    if (p_cid) p_cid[o + (p - lo)] = perm[(int32_t)cid[p] + tile * kt];
                     if (p_val) p_val[o + (p - lo)] = v64[p];
                 }
                 o += hi - lo;
@@ -436,7 +356,7 @@ hipError_t ivf_export(const sivf_ivf* f, int64_t* term_ptr, int32_t* split, int3
     int64_t blocks = (d * 64 + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_exp_fill, dim3((unsigned)blocks), dim3(256), 0, s, f->seg, f->mid, f->cid, f->v64, d, f->T,
-                       f->kt, term_ptr, p_cid, p_val);
+                       f->kt, f->perm, term_ptr, p_cid, p_val);
     return hipGetLastError();
 }
 

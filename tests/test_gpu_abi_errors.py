@@ -98,13 +98,6 @@ def test_null_pointers_and_bad_options():
     opt.posting_dtype = N.SIVF_F64                                # postings are f32 or bf16
     assert lib.sivf_create(ctypes.byref(h), 0, None, ctypes.byref(opt)) == -1
     lib.sivf_default_options(ctypes.byref(opt))
-    opt.icp_compact = 2                                           # 0 or 1
-    assert lib.sivf_create(ctypes.byref(h), 0, None, ctypes.byref(opt)) == -1
-    opt.icp_compact = 1
-    opt.icp_head_moving = 2.5                                     # < 0 (automatic) or [0, 2]
-    assert lib.sivf_create(ctypes.byref(h), 0, None, ctypes.byref(opt)) == -1
-    opt.icp_head_moving = float("nan")
-    assert lib.sivf_create(ctypes.byref(h), 0, None, ctypes.byref(opt)) == -1
     assert lib.sivf_create(ctypes.byref(h), 999, None, None) == -7
     assert lib.sivf_create(None, 0, None, None) == -1
     ctx = _ctx()

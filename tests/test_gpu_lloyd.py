@@ -199,21 +199,25 @@ def test_more_than_65536_centroids():
 
 
 @pytest.mark.parametrize("posting", ["fp32", "bf16"])
-def test_compacted_icp_tiles(posting):
-    # Objects in the ICP branch sum into a tile of just the moving centroids
-    # where fewer than a quarter of a tile's centroids move.  k = 300 in
-    # 64-centroid tiles: 85% of the clusters are invariant by iteration 6.
-    # k = 5,000 in 4096-centroid tiles: 542 moving centroids in tile 0 at
-    # iteration 3 (several batches), then fewer than 256 (one batch).  With
-    # and without compaction the runs match the oracle step by step.
-    log("compacted ICP tiles posting=%s" % posting)
+def test_moving_prefix_tiles(posting):
+    # The file numbers the moving centroids first: objects in the ICP branch
+    # read the moving prefix of each tile and skip the tiles past it.  k = 300
+    # in 64-centroid tiles: 85% of the clusters are invariant by iteration 6,
+    # so most launches are past the prefix and the boundary moves inside a
+    # tile.  k = 5,000 in one 4096-centroid tile and a ragged one: 542 moving
+    # centroids at iteration 3, then fewer than one 512-centroid batch.  With
+    # head rows and without, one tile per launch and all in one launch, the
+    # runs match the oracle step by step (the exported file is compared in
+    # centroid ids).
+    log("moving-prefix tiles posting=%s" % posting)
     for (n, d, lam, k, kt, it, seed) in ((6000, 1500, 25, 300, 64, 14, 113), (20000, 3000, 30, 5000, 4096, 6, 115)):
         c = synth.make_corpus(n, d, lam, 1.0, np.float32, seed=seed)
         ids = synth.init_ids(c.n, k, 19)
-        for compact in (True, False):
-            ctx = _ctx(k_tile=kt, posting_dtype=posting, head_density=0.2, icp_compact=compact)
-            tr, st = lloyd_parity(ctx, _X(c), c, k, ids, it)
-            assert sum(s["icp_objects"] for s in st) > 0 and max(s["head_rows"] for s in st) > 0
+        for hd, tpl in ((0.2, 0), (0.0, 0), (0.2, 64)):
+            ctx = _ctx(k_tile=kt, posting_dtype=posting, head_density=hd, tiles_per_launch=tpl)
+            tr, st = lloyd_parity(ctx, _X(c), c, k, ids, it, check_ivf_every=3)
+            assert sum(s["icp_objects"] for s in st) > 0
+            assert (max(s["head_rows"] for s in st) > 0) == (hd > 0)
             ctx.close()
 
 
@@ -238,15 +242,15 @@ def test_tile_launch_split_with_ties_and_overflow(tiles_per_launch):
 
 @pytest.mark.parametrize("posting", ["fp32", "bf16"])
 def test_icp_objects_reading_head_rows(posting):
-    # Objects in the ICP branch read the dense head rows in every tile (0),
-    # in tiles where at least half the centroids move (0.5) or
-    # never (2): identical trajectories, flags and mult-add counts.
+    # Objects in the ICP branch read the moving prefix of the dense head rows
+    # (head rows at 0.2 or 0.05 of the centroids) or walk every term's list
+    # (none): identical trajectories, flags and mult-add counts.
     log("ICP objects and head rows, posting=%s" % posting)
     c = synth.make_corpus(20000, 3000, 40, 1.1, np.float32, seed=110)
     ids = synth.init_ids(20000, 400, 16)
     icp_seen = 0
-    for m in (0.0, 0.5, 2.0):
-        ctx = _ctx(k_tile=128, posting_dtype=posting, head_density=0.2, icp_head_moving=m)
+    for hd in (0.2, 0.05, 0.0):
+        ctx = _ctx(k_tile=128, posting_dtype=posting, head_density=hd)
         tr, st = lloyd_parity(ctx, _X(c), c, 400, ids, 12, check_ivf_every=4)
         icp_seen = max(icp_seen, sum(s["icp_objects"] for s in st))
         ctx.close()
