@@ -270,3 +270,63 @@ def test_relaxed_icp_trajectory(posting, tiles_per_launch):
     tr, st = lloyd_parity(ctx, _X(c), c, 300, ids, 12, mode="relaxed", check_ivf_every=4)
     assert sum(s["relaxed_objects"] for s in st) > 0
     assert [s["relaxed_objects"] for s in st] == [int((b == 2).sum()) for b in tr.branch[:len(st)]]
+
+
+@pytest.mark.parametrize("posting,mode,tiles_per_launch", [("fp32", "sivf", 0), ("bf16", "sivf", 0),
+                                                          ("fp32", "sivf", 64), ("fp32", "cbicp", 0)])
+def test_flag_patterns_on_a_built_file(posting, mode, tiles_per_launch):
+    # The file numbers the moving centroids first.  A file built from given
+    # centroids under chosen flags -- no moving centroid, all moving, one
+    # moving, alternating, a boundary inside a tile, random -- then one ICP
+    # assignment step: assignments, output flags and the mult-add count equal
+    # the oracle's, and the exported file (in centroid ids) equals the
+    # oracle's structured file.  k = 200 in tiles of 64, 64, 64 and 8.  The
+    # centroids are those after one update and the previous assignment that
+    # of the initial ones, so the restriction to moving centroids changes the
+    # result (147 to 743 objects end elsewhere than under the full argmax).
+    log("flag patterns posting=%s mode=%s tiles_per_launch=%d" % (posting, mode, tiles_per_launch))
+    c = synth.make_corpus(4000, 1200, 25, 1.0, np.float32, seed=117)
+    k = 200
+    a0, _, _ = oracle.assign(c, oracle.init_centroids(c, synth.init_ids(c.n, k, 21)))
+    cents, _ = oracle.update(c, a0, oracle.init_centroids(c, synth.init_ids(c.n, k, 21)))
+    own0 = oracle.pair_sims(c, cents, np.arange(c.n), a0)   # exact similarity to the own centroid now
+    rng = np.random.default_rng(5)
+    patterns = {
+        "none moving": np.ones(k, np.uint8),
+        "all moving": np.zeros(k, np.uint8),
+        "one moving": np.r_[np.ones(k - 1, np.uint8), np.zeros(1, np.uint8)],
+        "one invariant": np.r_[np.ones(1, np.uint8), np.zeros(k - 1, np.uint8)],
+        "alternating": (np.arange(k) % 2).astype(np.uint8),
+        "first 150 invariant": (np.arange(k) < 150).astype(np.uint8),
+        "random 70% invariant": (rng.random(k) < 0.7).astype(np.uint8),
+    }
+    X = _X(c)
+    dev = device()
+    ctx = _ctx(k_tile=64, posting_dtype=posting, head_density=0.2, filter_mode=mode,
+               tiles_per_launch=tiles_per_launch)
+    for name, lam in patterns.items():
+        log("  pattern: %s" % name)
+        ivf = ctx.build_centroid_ivf(torch.from_numpy(cents.ptr.astype(np.int64)).to(dev),
+                                     torch.from_numpy(cents.col.astype(np.int32)).to(dev),
+                                     torch.from_numpy(cents.val.astype(np.float64)).to(dev), c.d,
+                                     torch.from_numpy(lam).to(dev))
+        ex = ivf.export()
+        ref_ivf = oracle.build_ivf(cents, lam)
+        assert np.array_equal(ex["term_ptr"].cpu().numpy(), ref_ivf.term_ptr), name
+        assert np.array_equal(ex["split"].cpu().numpy(), ref_ivf.split), name
+        assert np.array_equal(ex["p_cid"].cpu().numpy(), ref_ivf.cid), name
+        assert np.array_equal(ex["p_val"].cpu().numpy(), ref_ivf.val), name
+        a = torch.from_numpy(a0.astype(np.int32)).to(dev)
+        own = torch.from_numpy(own0.astype(np.float32)).to(dev)
+        lam_out = torch.empty(k, dtype=torch.uint8, device=dev)
+        st = ctx.assign(X, ivf, 2, a, own, lam_out)
+        ref_a, _, _ = oracle.assign(c, cents, icp=True, lam_prev=lam, a_prev=a0, own_prev=own0)
+        got = a.cpu().numpy()
+        assert np.array_equal(got, ref_a), "%s: %d assignments differ" % (name, int((got != ref_a).sum()))
+        assert np.array_equal(lam_out.cpu().numpy(), oracle.mark_invariant(a0, ref_a, k, False)[0]), name
+        m_ref = oracle.multadds(c, ref_ivf, icp=True, lam_prev=lam, a_prev=a0,
+                                mode=oracle.MODE_CBICP if mode == "cbicp" else oracle.MODE_SIVF)
+        assert st["multadds"] == m_ref, "%s: multadds %d vs %d" % (name, st["multadds"], m_ref)
+        assert st["icp_objects"] == int(lam[a0].astype(bool).sum()), name
+        ivf.free()
+    ctx.close()
