@@ -195,8 +195,9 @@ sivf_status sivf_ivf_sizes(sivf_ctx* ctx, const sivf_ivf* ivf, int32_t* k_host, 
  *       the structured file in the paper's per-term layout: list of term s is
  *       [term_ptr[s], term_ptr[s+1]), moving part first with split[s] entries,
  *       each part in ascending centroid id.
- * The library's own in-memory layout additionally splits each list by
- * centroid tile; this export re-joins the tiles. */
+ * The library's own in-memory layout renumbers the centroids (moving ones
+ * first, each group in ascending id) and splits each list by tile of that
+ * numbering; this export re-joins the tiles and maps back to centroid ids. */
 sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* ivf, int64_t* c_ptr, int32_t* c_col,
                             double* c_val, uint8_t* lambda, int64_t* term_ptr, int32_t* split,
                             int32_t* p_cid, double* p_val);
