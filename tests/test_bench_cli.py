@@ -24,3 +24,23 @@ def test_walk_hash_prints():
     assert r.returncode == 0
     h = r.stdout.strip()
     assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_traffic_profile_used_only_for_matching_sources(tmp_path, monkeypatch):
+    # The stored HBM-traffic figure is reported only while the walk sources
+    # hash as they did when the counters were taken; else it is null.
+    sys.path.insert(0, ROOT)
+    try:
+        import bench
+    finally:
+        sys.path.remove(ROOT)
+    h = bench.walk_source_hash()
+    prof = tmp_path / "traffic.md"
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    assert bench.measured_traffic() is None                      # no profile
+    prof.write_text('text\nTRAFFIC_JSON {"walk_source_hash": "%s", "hbm_bytes_per_launch": 123.5}\n' % h)
+    assert bench.measured_traffic() == 123.5
+    prof.write_text('TRAFFIC_JSON {"walk_source_hash": "0000000000000000", "hbm_bytes_per_launch": 123.5}\n')
+    assert bench.measured_traffic() is None                      # taken on other kernel sources
+    prof.write_text('TRAFFIC_JSON {not json}\n')
+    assert bench.measured_traffic() is None
