@@ -272,9 +272,10 @@ def test_relaxed_icp_trajectory(posting, tiles_per_launch):
     assert [s["relaxed_objects"] for s in st] == [int((b == 2).sum()) for b in tr.branch[:len(st)]]
 
 
-@pytest.mark.parametrize("posting,mode,tiles_per_launch", [("fp32", "sivf", 0), ("bf16", "sivf", 0),
-                                                          ("fp32", "sivf", 64), ("fp32", "cbicp", 0)])
-def test_flag_patterns_on_a_built_file(posting, mode, tiles_per_launch):
+@pytest.mark.parametrize("posting,mode,tiles_per_launch,signed", [("fp32", "sivf", 0, False), ("bf16", "sivf", 0, False),
+                                                                 ("fp32", "sivf", 64, False),
+                                                                 ("fp32", "cbicp", 0, False), ("fp32", "sivf", 0, True)])
+def test_flag_patterns_on_a_built_file(posting, mode, tiles_per_launch, signed):
     # The file numbers the moving centroids first.  A file built from given
     # centroids under chosen flags -- no moving centroid, all moving, one
     # moving, alternating, a boundary inside a tile, random -- then one ICP
@@ -284,8 +285,12 @@ def test_flag_patterns_on_a_built_file(posting, mode, tiles_per_launch):
     # centroids are those after one update and the previous assignment that
     # of the initial ones, so the restriction to moving centroids changes the
     # result (147 to 743 objects end elsewhere than under the full argmax).
-    log("flag patterns posting=%s mode=%s tiles_per_launch=%d" % (posting, mode, tiles_per_launch))
+    # Signed values take the bound through each centroid's norm, looked up by
+    # centroid id from the position.
+    log("flag patterns posting=%s mode=%s tiles_per_launch=%d signed=%s" % (posting, mode, tiles_per_launch, signed))
     c = synth.make_corpus(4000, 1200, 25, 1.0, np.float32, seed=117)
+    if signed:
+        c.val *= np.where(np.random.default_rng(1).random(c.nnz) < 0.3, -1.0, 1.0).astype(c.val.dtype)
     k = 200
     a0, _, _ = oracle.assign(c, oracle.init_centroids(c, synth.init_ids(c.n, k, 21)))
     cents, _ = oracle.update(c, a0, oracle.init_centroids(c, synth.init_ids(c.n, k, 21)))
