@@ -30,11 +30,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+N_CU, CLOCK_GHZ = 256, 2.4   # MI355X compute units and peak engine clock
 POSTING_BYTES = {"fp32": 6, "bf16": 4}  # 2-byte centroid id + value
 WALK_KERNEL = "k_walk_fast<false, false>"   # FP32 postings, SIVF filter
-# counter-based HBM traffic of the walk, written from the rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs; used only while the kernel sources still hash the same
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_8m_k10k_hbm_traffic.md")
+# counter-based DRAM-side traffic of the walk, written from rocprofv3 --pmc
+# runs; used only while the kernel sources still hash the same
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_8m_k10k_dram_traffic.md")
 WALK_SOURCES = ["paper_2103_16141_amd/csrc/k_assign.hip", "paper_2103_16141_amd/csrc/internal.h",
                 "paper_2103_16141_amd/csrc/wave.h"]
 
@@ -49,18 +50,81 @@ def walk_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per walk launch from the committed counter profile, or None
-    when the profile is missing or was taken on other kernel sources."""
+    """DRAM-side bytes per walk launch from the committed counter profile
+    (record of the profile's TRAFFIC_JSON line), or None when the profile is
+    missing or was taken on other kernel sources."""
     try:
         with open(TRAFFIC_PROFILE) as fh:
             for line in fh:
                 if line.startswith("TRAFFIC_JSON "):
                     rec = json.loads(line[len("TRAFFIC_JSON "):])
                     if rec.get("walk_source_hash") == walk_source_hash():
-                        return rec["hbm_bytes_per_launch"]
+                        return rec
     except (OSError, ValueError, KeyError):
         pass
     return None
+
+
+PROBE_CASES = [
+    # name, kind (0 loads, 1 LDS read, 2 LDS write), bytes per lane, region, window, stride
+    ("l1_b32", 0, 4, 4 << 10, 4 << 10, 4 << 10),
+    ("l1_b64", 0, 8, 8 << 10, 8 << 10, 8 << 10),
+    ("l1_b128", 0, 16, 16 << 10, 16 << 10, 16 << 10),
+    ("l2_b128", 0, 16, 2 << 20, 256 << 10, 16 << 10),
+    ("mall_b128", 0, 16, 64 << 20, 8 << 20, 256 << 10),
+    ("hbm_b128", 0, 16, 2 << 30, 64 << 20, 16 << 20),
+    ("lds_read_b128", 1, 16, 0, 0, 0),
+    ("lds_write_b128", 2, 16, 0, 0, 0),
+]
+
+
+def run_probe(reps=3):
+    """Data rates of one compute unit's vector loads (from regions resident in
+    L1, L2, the memory-side cache and HBM) and of its LDS, from the kernels of
+    libsivf_probe.so: bytes per shader clock per CU, the shader clock from
+    s_memtime against the 100 MHz s_memrealtime, and GB/s over the device."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2103_16141_amd", "libsivf_probe.so"))
+    c_u32, vp = ctypes.c_uint32, ctypes.c_void_p
+    lib.sivf_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, vp, c_u32, c_u32, c_u32, ctypes.c_int, ctypes.c_int,
+                                   vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ulonglong)]
+    lib.sivf_probe_run.restype = ctypes.c_int
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    need = max(c[3] + c[4] for c in PROBE_CASES)
+    buf = torch.ones(need, dtype=torch.uint8, device="cuda")
+    scratch = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, kind, width, region, window, stride in PROBE_CASES:
+        blocks = n_cu * 8
+        rounds = 8192 if (kind or region <= (16 << 10)) else 2048
+        nbytes = ctypes.c_double()
+        clk = (ctypes.c_ulonglong * 2)()
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = lib.sivf_probe_run(kind, width, ctypes.c_void_p(buf.data_ptr()), region, window, stride, blocks,
+                                    rounds, ctypes.c_void_p(scratch.data_ptr()), ctypes.c_void_p(stream.cuda_stream),
+                                    ctypes.byref(nbytes), clk)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise RuntimeError("probe %s failed (%d)" % (name, rc))
+            ms = e0.elapsed_time(e1)
+            ghz = clk[0] / (clk[1] / 1e8) / 1e9 if clk[1] else float("nan")
+            rec = dict(gbs=nbytes.value / (ms * 1e-3) / 1e9, ms=ms, shader_ghz=ghz)
+            if best is None or rec["gbs"] > best["gbs"]:
+                best = rec
+        best["bytes_per_clk_cu"] = best["gbs"] * 1e9 / n_cu / (best["shader_ghz"] * 1e9)
+        out[name] = best
+        log("probe %s: %.0f GB/s, %.1f B/clk/CU at %.2f GHz" % (name, best["gbs"], best["bytes_per_clk_cu"],
+                                                                 best["shader_ghz"]))
+    del buf, scratch
+    torch.cuda.empty_cache()
+    return out
 
 
 def measured_copy_gbs(gib=1, reps=5):
@@ -187,9 +251,12 @@ def summarize(stats, wall, sizes, nnz, n, posting):
     t_walk = sum(s["t_walk_ms"] for s in stats) / 1e3
     t_update = sum(s["t_update_ms"] for s in stats) / 1e3
     bytes_ = sum(algorithmic_bytes(s, nnz, n, sizes["n_tiles"], posting) for s in stats)
+    loaded = sum(s["walk_bytes"] for s in stats)
     return dict(multadds=M, multadds_per_s=M / t_assign, s_per_iter=wall / len(stats),
                 assign_s=t_assign, walk_s=t_walk, update_s=t_update,
                 walk_multadds_per_s=M / t_walk, walk_algorithmic_gbs=bytes_ / t_walk / 1e9,
+                walk_loaded_bytes=loaded, walk_data_gbs=loaded / t_walk / 1e9,
+                walk_launches=sum(s["walk_launches"] for s in stats),
                 iter1_multadds_per_s=stats[0]["multadds"] / (stats[0]["t_assign_ms"] / 1e3),
                 rescored_objects=sum(s["rescored_objects"] for s in stats),
                 full_rescored=sum(s["full_rescored"] for s in stats),
@@ -198,7 +265,10 @@ def summarize(stats, wall, sizes, nnz, n, posting):
 
 def cpu_baseline(corpus, ids, k, budget_s=15.0):
     """FP64 oracle assignment (iteration 1, against the seeded initial centroids)
-    on a bounded sample of objects, in posting mult-adds per second."""
+    on a bounded sample of objects, in posting mult-adds per second: credited
+    with the same count M as the GPU (the structured file's postings of the
+    objects' terms), so it compares with the GPU's iteration-1 rate; the
+    oracle itself multiplies every term by all k centroids (dense FP64)."""
     import numpy as np
 
     import oracle
@@ -206,12 +276,14 @@ def cpu_baseline(corpus, ids, k, budget_s=15.0):
     cents = oracle.init_centroids(corpus, ids)
     _, per_row = oracle.multadds(corpus, oracle.build_ivf(cents, None), per_row=True)
     rng = np.random.default_rng(0)
-    m, rows_done, total_m, total_t = 256, 0, 0, 0.0
+    m, rows_done, total_m, total_t, total_terms = 256, 0, 0, 0.0, 0
+    lens = np.diff(corpus.row_ptr)
     while total_t < budget_s:
         rows = np.sort(rng.choice(corpus.n, m, replace=False))
         t0 = time.perf_counter()
         oracle.assign(corpus, cents, rows=rows)
         dt = time.perf_counter() - t0
+        total_terms += int(lens[rows].sum())
         total_m += int(per_row[rows].sum())
         total_t += dt
         rows_done += m
@@ -219,7 +291,9 @@ def cpu_baseline(corpus, ids, k, budget_s=15.0):
             m *= 2
     return dict(value=total_m / total_t, unit="mult-adds/s", cores=oracle.num_threads(), kind="oracle",
                 sample="%d uniformly drawn objects of the same workload at iteration 1 (FP64 inner products "
-                       "against the %d seeded initial centroids), %.1f s of CPU work" % (rows_done, k, total_t))
+                       "against the %d seeded initial centroids), %.1f s of CPU work" % (rows_done, k, total_t),
+                compare_with="iter1_multadds_per_s (the GPU's rate at the same iteration and count)",
+                dense_fp64_multadds_per_s=total_terms * k / total_t)
 
 
 def main():
@@ -244,9 +318,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 copies of 1 GiB (counter calibration for the traffic figure)")
     ap.add_argument("--print-walk-hash", action="store_true", help="print the walk kernel source hash and exit")
+    ap.add_argument("--probe", action="store_true", help="only run the data-rate probes and print them")
+    ap.add_argument("--skip-probe", action="store_true", help="skip the data-rate probes (roofline peak)")
     args = ap.parse_args()
     if args.print_walk_hash:
         print(walk_source_hash())
+        return
+    if args.probe:
+        print(json.dumps(run_probe()), flush=True)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -297,16 +376,38 @@ def main():
         soft = run_soft()
         log("soft form: fwd %.2f ms, bwd %.2f ms" % (soft["fwd_ms"], soft["bwd_ms"]))
     copy_gbs = measured_copy_gbs()
+    probe = None if args.skip_probe else run_probe()
 
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(corpus, ids, k, args.cpu_budget)
 
-    achieved = s32["walk_algorithmic_gbs"]
     # the walk is one kernel launch per group of tiles_per_launch centroid tiles
-    tpl = max(1, args.tiles_per_launch or 1)
-    launches = len(st32) * ((sizes["n_tiles"] + tpl - 1) // tpl)
+    launches = s32["walk_launches"]
     launch_ms = s32["walk_s"] * 1e3 / launches
+    # Roofline of the walk: the vector memory data path, whose load rate per CU
+    # (measured by the probe on L1-resident 16-byte loads) times 256 CUs at the
+    # 2.4 GHz peak clock is the peak; achieved = bytes the walk's vector loads
+    # request (counted by the kernel) over its launch time.
+    achieved = s32["walk_data_gbs"]
+    peak = probe["l1_b128"]["bytes_per_clk_cu"] * N_CU * CLOCK_GHZ if probe else None
+    traffic = measured_traffic()
+    dram = None
+    if traffic:
+        dram_gbs = traffic["dram_bytes_per_launch"] / (traffic["launch_ms"] * 1e-3) / 1e9
+        dram = dict(bytes_per_launch=traffic["dram_bytes_per_launch"], gbs=dram_gbs,
+                    frac_of_measured_copy=dram_gbs / copy_gbs, frac_of_hbm_peak=dram_gbs / HBM_PEAK_GBS,
+                    profile=os.path.relpath(TRAFFIC_PROFILE, ROOT))
+    roofline = {"bound": "vmem", "achieved": achieved, "peak": peak, "unit": "GB/s",
+                "frac": achieved / peak if peak else None,
+                "traffic": traffic["dram_bytes_per_launch"] if traffic else None,
+                "kernel": WALK_KERNEL, "launches": launches, "launch_avg_ms": launch_ms,
+                "bytes_per_launch": s32["walk_loaded_bytes"] / launches,
+                "peak_basis": "probe l1_b128 bytes/clk/CU x %d CUs x %.1f GHz" % (N_CU, CLOCK_GHZ),
+                "dram": dram,
+                "algorithmic_gbs": s32["walk_algorithmic_gbs"],
+                "algorithmic_frac_of_hbm_peak": s32["walk_algorithmic_gbs"] / HBM_PEAK_GBS,
+                "walk_avg_ms_per_iter": s32["walk_avg_ms"], "measured_copy_gbs": copy_gbs, "probe": probe}
     line = {
         "metric": "assign-step object-centroid mult-adds/s + s/iter at N=8M,k=10k; BF16 vs FP32",
         "value": s32["multadds_per_s"],
@@ -333,11 +434,7 @@ def main():
         "assign_s": s32["assign_s"], "update_s": s32["update_s"],
         "multadds_total": s32["multadds"],
         "bf16": out_bf16,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": WALK_KERNEL, "launches": launches, "launch_avg_ms": launch_ms,
-                     "algorithmic_bytes_per_launch": achieved * 1e9 * launch_ms * 1e-3,
-                     "walk_avg_ms_per_iter": s32["walk_avg_ms"], "measured_copy_gbs": copy_gbs},
+        "roofline": roofline,
         "soft": soft,
         "cpu_baseline": cpu,
     }

@@ -120,6 +120,10 @@ typedef struct {
                                    tile 1, ... so one tile's lists stay cache-
                                    resident; a value >= the tile count walks every
                                    tile of an object in one launch.  Same results. */
+    int32_t exact_objective;    /* 0 (default) or 1: sivf_assign also computes the
+                                   spherical objective of the new assignment against
+                                   the centroids it was made with, in FP64 from the
+                                   exact similarities (sivf_iter_stats.objective) */
 } sivf_options;
 
 /* Per-iteration statistics (host struct). */
@@ -139,6 +143,15 @@ typedef struct {
     float t_update_ms;           /* whole update step (means + structured file) */
     int64_t head_rows;           /* dense head rows the walk read (see head_density) */
     int64_t relaxed_objects;     /* objects that took the relaxed ICP branch */
+    double objective;            /* exact_objective: F(a^[r], mu^[r-1]) = sum_i rho(x_i,
+                                    mu^[r-1]_{a_i^[r]}), each rho the FP64 similarity of the
+                                    canonical order, summed in FP64 in a fixed order
+                                    (Section 1, the spherical objective); else NaN */
+    int64_t walk_bytes;          /* bytes requested by the fast pass's vector loads
+                                    (64 lanes x load width per load issued: posting and
+                                    head-row batches, segment records, staged terms) */
+    int32_t walk_launches;       /* fast-pass kernel launches of this step */
+    int32_t reserved;
 } sivf_iter_stats;
 
 typedef struct sivf_ctx sivf_ctx;  /* device, stream, options, workspace, last error */
@@ -161,8 +174,9 @@ const char* sivf_last_error(const sivf_ctx* ctx);
 
 /* Check X on the device: row_ptr monotone and consistent with nnz, columns in
  * [0, n_cols) and strictly ascending per row, values finite.  Waits for the
- * stream.  The other entry points run the same check on each X they have not
- * already checked (identified by its pointers and sizes). */
+ * stream.  Every other entry point that reads X runs the same check on each
+ * call (X may have been edited in place since the last one) before any kernel
+ * indexes with it; sivf_run_lloyd checks once per run. */
 sivf_status sivf_validate_csr(sivf_ctx* ctx, const sivf_csr* X);
 
 /* Initial centroids mu_j^(0) = x_{init_ids_host[j]} as stored (values widened to
@@ -205,10 +219,13 @@ sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* ivf, int64_t* c_ptr, 
 /* Assignment step r = iter (Alg. 4).  ivf holds mu^[r-1] structured by
  * lambda^[r-1] (the flags of the last update, all 0 after init).
  *  assign_inout int32[N]:  in a^[r-1] (ignored when iter == 1), out a^[r].
- *  own_sim_inout f32[N]:   in the values this call wrote at r-1 (ignored when
- *                          iter == 1); out the similarity of each object to its
- *                          new centroid (fast-pass value or FP64 re-score
- *                          rounded to FP32).
+ *  own_sim_inout f32[N]:   in the values this call wrote at r-1, or those of
+ *                          sivf_resume (ignored when iter == 1; read for the
+ *                          objects whose cluster is invariant, and trusted: a
+ *                          value farther from the exact similarity than the
+ *                          certificate's bound can give a wrong argmax); out
+ *                          the similarity of each object to its new centroid
+ *                          (fast-pass value or FP64 re-score rounded to FP32).
  *  own64_inout f64[N]:     RELAXED mode only (else may be NULL): in the values
  *                          this call wrote at r-1 (ignored when iter == 1);
  *                          out the exact FP64 similarity of each object to its
@@ -230,6 +247,28 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* ivf, i
  * their centroid bitwise.  stats_host optional (t_update_ms). */
 sivf_status sivf_update(sivf_ctx* ctx, const sivf_csr* X, const int32_t* assign,
                         const uint8_t* lambda, sivf_ivf* ivf_inout, sivf_iter_stats* stats_host);
+
+/* Restart a run between iterations (Alg. 1 from a saved state): the state
+ * after the update of iteration r-1 is the centroids mu^[r-1] and the last two
+ * assignments.  Builds the file of mu^[r-1] structured by lambda^[r-1], the
+ * flags of the clusters whose members are the same in a^[r-2] and a^[r-1]
+ * (Alg. 4, invariant clusters; all 0 when a_prev2 is NULL, i.e. r-1 = 1), and
+ * the own similarities the next sivf_assign(iter = r) reads.
+ *  centroids:     k x d CSR, SIVF_F64 values (copied), e.g. from sivf_ivf_export.
+ *  a_prev:        int32[N] a^[r-1]; a_prev2: int32[N] a^[r-2] or NULL.
+ *  *out:          receives the new file.
+ *  own_sim_out:   f32[N], rho(x_i, mu^[r-1]_{a_i}) in FP64 rounded to FP32.
+ *  own64_out:     f64[N] (RELAXED mode only, else may be NULL): that exact value
+ *                 where the object's cluster is invariant, +infinity elsewhere,
+ *                 so the first resumed step takes no relaxed branch (the
+ *                 similarity to the centroid before the last update is not part
+ *                 of the state); assignments are unaffected.
+ * Continuing with sivf_assign(iter = r, assign_inout = a^[r-1], own_sim_out,
+ * own64_out) and sivf_update reproduces the uninterrupted run's assignments,
+ * flags, centroids and mult-add counts (RELAXED: counts from step r+1 on).
+ * Waits for the stream. */
+sivf_status sivf_resume(sivf_ctx* ctx, const sivf_csr* X, const sivf_csr* centroids, const int32_t* a_prev,
+                        const int32_t* a_prev2, sivf_ivf** out, float* own_sim_out, double* own64_out);
 
 /* The Lloyd driver (Alg. 1 around Alg. 4 / Alg. 5): init from init_ids_host,
  * then for r = 1..max_iter: assign; stop if r >= 2 and nothing moved; update.

@@ -247,7 +247,38 @@ class LloydTrace:
     converged: bool = False
 
 
-def lloyd(corpus, k, ids, max_iter, icp=True, keep_centroids=False, count_multadds=True, relaxed=False):
+@dataclass
+class LloydState:
+    """Where a Lloyd run stands after the update of iteration r (Alg. 1): the
+    next assignment step is r + 1 and reads these values.
+
+    cents: mu^[r]; a: a^[r]; lam: lambda^[r] (from a^[r-1] and a^[r]);
+    own: rho of each object to mu^[r]_{a_i}.  For an object whose cluster is
+    invariant (lam[a_i] = 1) that centroid did not change, so this is the
+    cached own similarity the ICP branch starts from; the other objects' values
+    are not read in the SIVF, IVF and IVF-CBICP modes.
+    """
+    r: int
+    cents: Centroids
+    a: np.ndarray
+    own: np.ndarray
+    lam: np.ndarray
+
+
+def resume_state(corpus, cents: Centroids, a_prev, a_prev2=None, r=None) -> LloydState:
+    """State to continue a run from its last two assignments and the centroids
+    the last update produced (Alg. 1 restarted between iterations):
+    lambda^[r] from (a^[r-1], a^[r]) -- all zero when a_prev2 is None, i.e.
+    r = 1 -- and the own similarities rho(x_i, mu^[r]_{a_i}) recomputed with
+    the same fold as the assignment step."""
+    a_prev = np.ascontiguousarray(a_prev, np.int32)
+    lam, _ = mark_invariant(a_prev2, a_prev, cents.k, first=a_prev2 is None)
+    own = pair_sims(corpus, cents, np.arange(corpus.n), a_prev)
+    return LloydState(r if r is not None else (1 if a_prev2 is None else 2), cents, a_prev, own, lam)
+
+
+def lloyd(corpus, k, ids, max_iter, icp=True, keep_centroids=False, count_multadds=True, relaxed=False,
+          start: LloydState | None = None, on_iter=None):
     """Spherical Lloyd with SIVF bookkeeping (Alg. 1 driver around Alg. 4 / Alg. 5).
 
     Iteration r: assignment against mu^[r-1] (ICP mode from r >= 2 when icp;
@@ -255,32 +286,54 @@ def lloyd(corpus, k, ids, max_iter, icp=True, keep_centroids=False, count_multad
     similarity to it decreasing compare moving centroids only), invariance
     flags lambda^[r], stop after an assignment step r >= 2 that moved nothing,
     else update to mu^[r].
+
+    start: continue after iteration start.r instead of starting from the
+    seeded objects (ids is then unused); the trace lists iterations
+    start.r + 1 .. in order.  Relaxed ICP needs the similarities to the
+    previous centroids, which a restart does not have, so it cannot resume.
+    on_iter(info): called after each assignment step with a dict holding r, a,
+    own, lam, moved, multadds, branch and, once the update ran, cents (mu^[r]).
     """
-    cents = init_centroids(corpus, ids)
+    if start is not None and relaxed:
+        raise ValueError("relaxed ICP cannot resume from a saved state")
+    if start is None:
+        cents = init_centroids(corpus, ids)
+        a_prev = own_prev = lam_prev = None
+        r0 = 0
+    else:
+        cents, a_prev, own_prev, lam_prev, r0 = start.cents, start.a, start.own, start.lam, start.r
     tr = LloydTrace()
-    a_prev = own_prev = lam_prev = None
-    for r in range(1, max_iter + 1):
+    for r in range(r0 + 1, max_iter + 1):
         if keep_centroids:
             tr.centroids.append(cents)
         use_icp = icp and r >= 2
         a, own, _, branch = assign(corpus, cents, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev, own_prev=own_prev,
                                    relaxed=relaxed, want_branch=True)
         tr.branch.append(branch)
+        m = None
         if count_multadds:
             ivf = build_ivf(cents, lam_prev)
-            tr.multadds.append(multadds(corpus, ivf, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev,
-                                        branch=branch if use_icp else None))
+            m = multadds(corpus, ivf, icp=use_icp, lam_prev=lam_prev, a_prev=a_prev,
+                         branch=branch if use_icp else None)
+            tr.multadds.append(m)
+            del ivf
         lam, moved = mark_invariant(a_prev, a, k, first=(r == 1))
         tr.assign.append(a)
         tr.own.append(own)
         tr.lam.append(lam)
         tr.moved.append(moved)
         tr.iters = r
+        info = dict(r=r, a=a, own=own, lam=lam, moved=moved, multadds=m, branch=branch, cents=None)
         if r >= 2 and moved == 0:
             tr.converged = True
+            if on_iter:
+                on_iter(info)
             break
         cents, _ = update(corpus, a, cents)
         a_prev, own_prev, lam_prev = a, own, lam
+        if on_iter:
+            info["cents"] = cents
+            on_iter(info)
     tr.final = cents
     return tr
 

@@ -23,7 +23,8 @@ class sivf_csr(ctypes.Structure):
 class sivf_options(ctypes.Structure):
     _fields_ = [("posting_dtype", ctypes.c_int), ("filter_mode", ctypes.c_int32), ("k_tile", ctypes.c_int32),
                 ("certify", ctypes.c_int32), ("workspace_cap_bytes", ctypes.c_size_t),
-                ("head_density", ctypes.c_float), ("tiles_per_launch", ctypes.c_int32)]
+                ("head_density", ctypes.c_float), ("tiles_per_launch", ctypes.c_int32),
+                ("exact_objective", ctypes.c_int32)]
 
 
 class sivf_iter_stats(ctypes.Structure):
@@ -32,7 +33,8 @@ class sivf_iter_stats(ctypes.Structure):
                 ("rescored_candidates", ctypes.c_int64), ("full_rescored", ctypes.c_int64),
                 ("objective_fast", ctypes.c_double), ("t_walk_ms", ctypes.c_float),
                 ("t_assign_ms", ctypes.c_float), ("t_update_ms", ctypes.c_float), ("head_rows", ctypes.c_int64),
-                ("relaxed_objects", ctypes.c_int64)]
+                ("relaxed_objects", ctypes.c_int64), ("objective", ctypes.c_double), ("walk_bytes", ctypes.c_int64),
+                ("walk_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -74,6 +76,7 @@ def load(path: str = LIB_PATH):
         "sivf_assign": ([vp, csr_p, vp, i32, vp, vp, vp, vp, stats_p], st),
         "sivf_update": ([vp, csr_p, vp, vp, vp, stats_p], st),
         "sivf_run_lloyd": ([vp, csr_p, i32, vp, i32, vp, vp, P(vp), stats_p, P(i32)], st),
+        "sivf_resume": ([vp, csr_p, csr_p, vp, vp, P(vp), vp, vp], st),
         "sivf_soft_assign_fwd": ([vp, csr_p, vp, i32, f32, vp, P(ctypes.c_double)], st),
         "sivf_soft_assign_bwd": ([vp, csr_p, vp, i32, f32, vp, f32, vp, vp], st),
     }

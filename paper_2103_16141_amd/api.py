@@ -115,7 +115,8 @@ class Ivf:
 
 class Context:
     def __init__(self, device=0, posting_dtype="fp32", filter_mode="sivf", k_tile=0, certify=True,
-                 workspace_cap_bytes=0, stream=None, head_density=None, tiles_per_launch=None):
+                 workspace_cap_bytes=0, stream=None, head_density=None, tiles_per_launch=None,
+                 exact_objective=False):
         lib = N.load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         idx = self.device.index if self.device.index is not None else 0
@@ -131,6 +132,7 @@ class Context:
             opt.head_density = float(head_density)
         if tiles_per_launch is not None:
             opt.tiles_per_launch = int(tiles_per_launch)
+        opt.exact_objective = 1 if exact_objective else 0
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -190,6 +192,20 @@ class Context:
                                        ctypes.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
+    def resume(self, X: DeviceCsr, centroids: DeviceCsr, a_prev, a_prev2=None):
+        """Restart after the update of iteration r-1 from (mu^[r-1], a^[r-1],
+        a^[r-2]): returns (file structured by lambda^[r-1], own similarities
+        f32[N], exact own similarities f64[N] or None)."""
+        n = X.n_rows
+        own = torch.empty(n, dtype=torch.float32, device=self.device)
+        relaxed = self.opt.filter_mode == N.SIVF_MODE_RELAXED
+        own64 = torch.empty(n, dtype=torch.float64, device=self.device) if relaxed else None
+        s, c = X.struct(), centroids.struct()
+        h = ctypes.c_void_p()
+        self._chk(N.load().sivf_resume(self.handle, ctypes.byref(s), ctypes.byref(c), _ptr(a_prev), _ptr(a_prev2),
+                                       ctypes.byref(h), _ptr(own), _ptr(own64)))
+        return Ivf(self, h), own, own64
+
     def run_lloyd(self, X: DeviceCsr, k: int, init_ids, max_iter: int, keep_centroids=True):
         ids = np.ascontiguousarray(init_ids, dtype=np.int32)
         a = torch.empty(X.n_rows, dtype=torch.int32, device=self.device)
@@ -235,6 +251,18 @@ class Lloyd:
         relaxed = ctx.opt.filter_mode == N.SIVF_MODE_RELAXED
         self.own64 = torch.zeros(X.n_rows, dtype=torch.float64, device=dev) if relaxed else None
         self.r = 0
+
+    @classmethod
+    def resume(cls, ctx: Context, X: DeviceCsr, centroids: DeviceCsr, r_done: int, a_prev, a_prev2=None):
+        """A driver continuing after the update of iteration r_done from the
+        centroids mu^[r_done] and the assignments a^[r_done], a^[r_done - 1]."""
+        self = cls.__new__(cls)
+        self.ctx, self.X, self.k = ctx, X, centroids.n_rows
+        self.ivf, self.own, self.own64 = ctx.resume(X, centroids, a_prev, a_prev2)
+        self.a = a_prev.clone()
+        self.lam = torch.zeros(self.k, dtype=torch.uint8, device=ctx.device)
+        self.r = r_done
+        return self
 
     def assign(self):
         self.r += 1

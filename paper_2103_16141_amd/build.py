@@ -14,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsivf.so")
+# data-rate probes for the benchmark's roofline (not part of libsivf.so)
+PROBE_SRC = "probe.hip"
+PROBE_LIB = os.path.join(HERE, "libsivf_probe.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["k_util.hip", "k_ivf.hip", "k_assign.hip", "k_update.hip", "k_soft.hip", "api.cpp"]
@@ -59,6 +62,14 @@ def build(force: bool = False, verbose: bool = False) -> str:
         if r.returncode != 0:
             raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
         os.replace(tmp, LIB)
+    po = _compile(PROBE_SRC, force)
+    if force or not os.path.exists(PROBE_LIB) or os.path.getmtime(PROBE_LIB) < os.path.getmtime(po):
+        tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", po, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+        os.replace(tmp, PROBE_LIB)
     if verbose:
         print(LIB)
     return LIB

@@ -119,40 +119,32 @@ sivf_status check_csr_args(sivf_ctx* ctx, const sivf_csr* X, const char* what) {
     return SIVF_OK;
 }
 
-sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out, bool force) {
+// Validate X on the device on every call that reads it.  Nothing is cached:
+// X may be edited in place between calls (same pointers, new contents), and
+// both the column range (used as an index by the walk) and the sign of the
+// values (which selects the certificate's error bound) must hold for the
+// contents the kernels will read.  One coalesced pass over the nonzeros.
+sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out) {
     STCHK(check_csr_args(ctx, X, "X"));
     const int f64 = X->val_dtype == SIVF_F64;
-    const bool same = ctx->vx_rp == X->row_ptr && ctx->vx_col == X->col && ctx->vx_val == X->val &&
-                      ctx->vx_n == X->n_rows && ctx->vx_d == X->n_cols && ctx->vx_nnz == X->nnz &&
-                      ctx->vx_f64 == f64;
-    if (!same || force) {
-        unsigned long long* flags = nullptr;
-        STCHK(ws(ctx, "vflags", 4, &flags));
-        unsigned long long init[3] = {0ull, ~0ull, 0ull};
-        HIPCHK(ctx, hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
-        if (X->n_rows > 0)
-            HIPCHK(ctx, validate_csr(X->row_ptr, X->col, X->val, f64, X->n_rows, X->n_cols, X->nnz, flags, ctx->stream));
-        unsigned long long h[3];
-        HIPCHK(ctx, hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        if (X->n_rows == 0) {
-            int64_t rp0 = 0;
-            HIPCHK(ctx, hipMemcpy(&rp0, X->row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost));
-            if (rp0 != 0 || X->nnz != 0) return fail(ctx, SIVF_E_UNSORTED, "X: empty matrix with row_ptr[0] != 0 or nnz != 0");
-        }
-        if (h[0] & 1ull) return fail(ctx, SIVF_E_UNSORTED, "X: row %llu has unsorted/duplicate columns or a decreasing row_ptr", h[1]);
-        if (h[0] & 8ull) return fail(ctx, SIVF_E_UNSORTED, "X: row_ptr[0] != 0 or row_ptr[n] != nnz");
-        if (h[0] & 2ull) return fail(ctx, SIVF_E_RANGE, "X: row %llu has a column outside [0, %lld)", h[1], (long long)X->n_cols);
-        if (h[0] & 4ull) return fail(ctx, SIVF_E_NONFINITE, "X: row %llu has a non-finite value", h[1]);
-        ctx->vx_rp = X->row_ptr;
-        ctx->vx_col = X->col;
-        ctx->vx_val = X->val;
-        ctx->vx_n = X->n_rows;
-        ctx->vx_d = X->n_cols;
-        ctx->vx_nnz = X->nnz;
-        ctx->vx_f64 = f64;
-        ctx->vx_nonneg = h[2] ? 0 : 1;
+    unsigned long long* flags = nullptr;
+    STCHK(ws(ctx, "vflags", 4, &flags));
+    unsigned long long init[3] = {0ull, ~0ull, 0ull};
+    HIPCHK(ctx, hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+    if (X->n_rows > 0)
+        HIPCHK(ctx, validate_csr(X->row_ptr, X->col, X->val, f64, X->n_rows, X->n_cols, X->nnz, flags, ctx->stream));
+    unsigned long long h[3];
+    HIPCHK(ctx, hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (X->n_rows == 0) {
+        int64_t rp0 = 0;
+        HIPCHK(ctx, hipMemcpy(&rp0, X->row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (rp0 != 0 || X->nnz != 0) return fail(ctx, SIVF_E_UNSORTED, "X: empty matrix with row_ptr[0] != 0 or nnz != 0");
     }
+    if (h[0] & 1ull) return fail(ctx, SIVF_E_UNSORTED, "X: row %llu has unsorted/duplicate columns or a decreasing row_ptr", h[1]);
+    if (h[0] & 8ull) return fail(ctx, SIVF_E_UNSORTED, "X: row_ptr[0] != 0 or row_ptr[n] != nnz");
+    if (h[0] & 2ull) return fail(ctx, SIVF_E_RANGE, "X: row %llu has a column outside [0, %lld)", h[1], (long long)X->n_cols);
+    if (h[0] & 4ull) return fail(ctx, SIVF_E_NONFINITE, "X: row %llu has a non-finite value", h[1]);
     out->n = X->n_rows;
     out->d = X->n_cols;
     out->nnz = X->nnz;
@@ -160,7 +152,7 @@ sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out, bool force) {
     out->col = X->col;
     out->val = X->val;
     out->f64 = f64;
-    out->nonneg = ctx->vx_nonneg;
+    out->nonneg = h[2] ? 0 : 1;
     return SIVF_OK;
 }
 
@@ -299,7 +291,7 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
     STCHK(ws(ctx, "ivf_pre1", W64 * f->d, &w.pre1));
     STCHK(ws(ctx, "ivf_cnt", nseg2, &w.cnt));
     STCHK(ws(ctx, "ivf_off", nseg2 + 1, &w.off));
-    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(std::max<int64_t>(nseg2, f->k + 1), ctx->vx_n + 1)) + 8,
+    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(nseg2, f->k + 1)) + 8,
              &w.scan_ws));
     int64_t* pmv = nullptr;
     int64_t* pmvpre = nullptr;
@@ -339,105 +331,39 @@ sivf_status restructure(sivf_ctx* ctx, sivf_ivf* f) {
     HIPCHK(ctx, ivf_fill(f->cur, f->k, f->d, f->kt, f->T, f->iperm, f->nmv, w, f->cid, f->v32, f->v16, f->v64,
                          ctx->stream));
     f->H = 0;
-    if (f->head) {
+    if (f->head && H > 0) {
         const int64_t kpad = (int64_t)f->T * head_ktp(f->kt), esz = f->pdt == SIVF_BF16 ? 2 : 4;
-        // rows beyond the cap are not built: the walk then reads every list
-        if (H > 0 && H * kpad * esz <= kHeadCapBytes) {
-            if (H > f->hcap) {
-                HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-                dev_free(ctx, f->hval, (size_t)(f->hcap * kpad * esz), &f->bytes);
-                f->hval = nullptr;
-                f->hcap = 0;
-                const int64_t c = std::min<int64_t>(H + H / 8 + 16, kHeadCapBytes / (kpad * esz));
-                STCHK(dev_alloc(ctx, &f->hval, (size_t)(c * kpad * esz), &f->bytes));
-                f->hcap = c;
-            }
-            HIPCHK(ctx, head_fill(f->cur, f->k, f->head, f->iperm, kpad, f->kt, head_ktp(f->kt), H,
-                                  f->pdt == SIVF_BF16, f->hval, ctx->stream));
-            f->H = H;
+        // every row is addressed through a descriptor of its own, so the rows
+        // together may exceed 4 GiB; kHeadMaxBytes only bounds the request
+        if (H * kpad * esz > kHeadMaxBytes)
+            return fail(ctx, SIVF_E_UNSUPPORTED,
+                        "dense head rows would take %lld bytes (%lld rows), above %lld; raise head_density",
+                        (long long)(H * kpad * esz), (long long)H, (long long)kHeadMaxBytes);
+        if (H > f->hcap) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            dev_free(ctx, f->hval, (size_t)(f->hcap * kpad * esz), &f->bytes);
+            f->hval = nullptr;
+            f->hcap = 0;
+            const int64_t c = std::min<int64_t>(H + H / 8 + 16, std::min<int64_t>(f->d, kHeadMaxBytes / (kpad * esz)));
+            STCHK(dev_alloc(ctx, &f->hval, (size_t)(c * kpad * esz), &f->bytes));
+            f->hcap = c;
         }
+        HIPCHK(ctx, head_fill(f->cur, f->k, f->head, f->iperm, kpad, f->kt, head_ktp(f->kt), H, f->pdt == SIVF_BF16,
+                              f->hval, ctx->stream));
+        f->H = H;
     }
     HIPCHK(ctx, seg_records(f->seg, f->mid, f->H > 0 ? f->head : nullptr, f->d, f->T, f->rec, ctx->stream));
-    if (!f->nonneg) HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
+    // norm bounds for the signed-data certificate: needed whenever the X of a
+    // later call has a negative value, whatever the centroids' signs
+    HIPCHK(ctx, centroid_norms(f->cur, f->k, f->cnorm, ctx->stream));
     return SIVF_OK;
 }
 
-}  // namespace
+// ------------------------------------------------------------ step bodies
+// The ABI entry points validate their arguments (X on every call) and then
+// run these; the Lloyd driver validates X once and calls them directly.
 
-// =========================================================================== ABI
-extern "C" {
-
-sivf_status sivf_default_options(sivf_options* opt) {
-    if (!opt) return SIVF_E_INVALID;
-    opt->posting_dtype = SIVF_F32;
-    opt->filter_mode = SIVF_MODE_SIVF;
-    opt->k_tile = 0;
-    opt->certify = 1;
-    opt->workspace_cap_bytes = 0;
-    opt->head_density = 0.5f;
-    opt->tiles_per_launch = 0;
-    return SIVF_OK;
-}
-
-sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf_options* opt) {
-    if (!out) return SIVF_E_INVALID;
-    *out = nullptr;
-    sivf_options o;
-    sivf_default_options(&o);
-    if (opt) o = *opt;
-    if (o.posting_dtype != SIVF_F32 && o.posting_dtype != SIVF_BF16) return SIVF_E_INVALID;
-    if (o.filter_mode < 0 || o.filter_mode > 3) return SIVF_E_INVALID;
-    if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
-    if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
-    if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
-    sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
-    if (!ctx) return SIVF_E_NOMEM;
-    ctx->device = device;
-    ctx->stream = (hipStream_t)hip_stream;
-    ctx->opt = o;
-    DevGuard g(device);
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
-        ctx->n_cu = ncu;
-    for (auto& e : ctx->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            delete ctx;
-            return SIVF_E_HIP;
-        }
-    }
-    *out = ctx;
-    return SIVF_OK;
-}
-
-sivf_status sivf_destroy(sivf_ctx* ctx) {
-    if (!ctx) return SIVF_OK;
-    DevGuard g(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->ws) (void)hipFree(kv.second.first);
-    for (auto& e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
-    delete ctx;
-    return SIVF_OK;
-}
-
-const char* sivf_last_error(const sivf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-sivf_status sivf_validate_csr(sivf_ctx* ctx, const sivf_csr* X) {
-    if (!ctx) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    Csr c;
-    return validate(ctx, X, &c, true);
-}
-
-sivf_status sivf_init_centroids(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const int32_t* init_ids_host,
-                                sivf_ivf** out) {
-    if (!ctx) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    if (!out || !init_ids_host) return fail(ctx, SIVF_E_INVALID, "NULL argument");
-    Csr Xc;
-    STCHK(validate(ctx, X, &Xc, false));
+sivf_status init_impl(sivf_ctx* ctx, const Csr& Xc, int32_t k, const int32_t* init_ids_host, sivf_ivf** out) {
     if (k < 1 || k > Xc.n) return fail(ctx, SIVF_E_SHAPE, "need 1 <= k <= N (k=%d, N=%lld)", k, (long long)Xc.n);
     for (int32_t j = 0; j < k; ++j)
         if (init_ids_host[j] < 0 || init_ids_host[j] >= Xc.n)
@@ -451,7 +377,7 @@ sivf_status sivf_init_centroids(sivf_ctx* ctx, const sivf_csr* X, int32_t k, con
     if (st == SIVF_OK) st = ws(ctx, "init_ids", k, &ids);
     if (st == SIVF_OK) st = ws(ctx, "init_lens", k, &lens);
     if (st == SIVF_OK) st = ws(ctx, "init_scan", k + 1, &scan);
-    if (st == SIVF_OK) st = ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(k + 1, Xc.n + 1)) + 8, &sws);
+    if (st == SIVF_OK) st = ws(ctx, "scan_ws", scan_ws_elems(k + 1) + 8, &sws);
     int64_t total = 0;
     auto H = [&](hipError_t e) {
         if (st == SIVF_OK && e != hipSuccess) st = fail(ctx, SIVF_E_HIP, "HIP error: %s", hipGetErrorString(e));
@@ -479,14 +405,11 @@ sivf_status sivf_init_centroids(sivf_ctx* ctx, const sivf_csr* X, int32_t k, con
     return SIVF_OK;
 }
 
-sivf_status sivf_build_centroid_ivf(sivf_ctx* ctx, const sivf_csr* C, const uint8_t* lambda, sivf_ivf** out) {
-    if (!ctx) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    if (!out) return fail(ctx, SIVF_E_INVALID, "NULL out");
+// lambda: device flags (NULL = all moving), copied into the file
+sivf_status build_impl(sivf_ctx* ctx, const sivf_csr* C, const uint8_t* lambda, sivf_ivf** out) {
     STCHK(check_csr_args(ctx, C, "centroids"));
     if (C->val_dtype != SIVF_F64) return fail(ctx, SIVF_E_INVALID, "centroid values must be SIVF_F64");
     if (C->n_rows < 1 || C->n_rows > INT32_MAX) return fail(ctx, SIVF_E_SHAPE, "need 1 <= k <= 2^31-1");
-    // validate with the same kernel (does not disturb the X cache)
     unsigned long long* flags = nullptr;
     STCHK(ws(ctx, "vflags", 4, &flags));
     unsigned long long init[3] = {0ull, ~0ull, 0ull};
@@ -520,63 +443,13 @@ sivf_status sivf_build_centroid_ivf(sivf_ctx* ctx, const sivf_csr* C, const uint
     return SIVF_OK;
 }
 
-sivf_status sivf_ivf_free(sivf_ctx* ctx, sivf_ivf* ivf) {
-    if (!ivf) return SIVF_OK;
-    if (!ctx) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    free_file(ctx, ivf);
-    return SIVF_OK;
-}
-
-sivf_status sivf_ivf_sizes(sivf_ctx* ctx, const sivf_ivf* f, int32_t* k_host, int64_t* d_host, int64_t* nnz_host,
-                           int32_t* n_tiles_host, int32_t* k_tile_host) {
-    if (!ctx || !f) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    if (k_host) *k_host = f->k;
-    if (d_host) *d_host = f->d;
-    if (nnz_host) *nnz_host = f->P;
-    if (n_tiles_host) *n_tiles_host = f->T;
-    if (k_tile_host) *k_tile_host = f->kt;
-    return SIVF_OK;
-}
-
-sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* f, int64_t* c_ptr, int32_t* c_col, double* c_val,
-                            uint8_t* lambda, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val) {
-    if (!ctx || !f) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    if ((c_col || c_val) && !c_ptr) return fail(ctx, SIVF_E_INVALID, "c_col/c_val need c_ptr");
-    if ((p_cid || p_val) && !term_ptr) return fail(ctx, SIVF_E_INVALID, "p_cid/p_val need term_ptr");
-    int64_t* sws = nullptr;
-    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(std::max<int64_t>(f->k, f->d) + 1, ctx->vx_n + 1)) + 8,
-             &sws));
-    if (c_ptr) {
-        HIPCHK(ctx, exclusive_scan_i64(f->cur.nnz, c_ptr, f->k, sws, ctx->stream));
-        if (c_col || c_val) HIPCHK(ctx, store_export(f->cur, f->k, c_ptr, c_col, c_val, ctx->stream));
-    }
-    if (lambda) HIPCHK(ctx, hipMemcpyAsync(lambda, f->lam, (size_t)f->k, hipMemcpyDeviceToDevice, ctx->stream));
-    if (term_ptr || split) {
-        int64_t* cnt = nullptr;
-        STCHK(ws(ctx, "exp_cnt", f->d, &cnt));
-        HIPCHK(ctx, ivf_export(f, term_ptr, split, p_cid, p_val, cnt, sws, ctx->stream));
-    }
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return SIVF_OK;
-}
-
-sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
+// Assignment step r = iter (Alg. 4) of X against the file f.
+sivf_status assign_impl(sivf_ctx* ctx, const Csr& Xc, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
                         float* own_sim_inout, double* own64_inout, uint8_t* lambda_out, sivf_iter_stats* stats_host) {
-    if (!ctx) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    if (!f || !assign_inout || !own_sim_inout || !lambda_out) return fail(ctx, SIVF_E_INVALID, "NULL argument");
-    const int relaxed = ctx->opt.filter_mode == SIVF_MODE_RELAXED;
-    if (relaxed && !own64_inout) return fail(ctx, SIVF_E_INVALID, "the RELAXED filter needs own64_inout");
-    if (iter < 1) return fail(ctx, SIVF_E_INVALID, "iter must be >= 1");
-    Csr Xc;
-    STCHK(validate(ctx, X, &Xc, false));
     if (Xc.d != f->d) return fail(ctx, SIVF_E_SHAPE, "X has %lld columns, centroids %lld", (long long)Xc.d, (long long)f->d);
     const int64_t n = Xc.n;
     const int32_t k = f->k;
+    const int relaxed = ctx->opt.filter_mode == SIVF_MODE_RELAXED;
     const int icp_on = iter >= 2 && ctx->opt.filter_mode != SIVF_MODE_IVF;
     if (iter >= 2) STCHK(check_assign(ctx, assign_inout, n, k, "assign_inout (a^[r-1])"));
     const int64_t qcap = std::max<int64_t>(1024, n / 4);
@@ -597,7 +470,10 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     STCHK(ws(ctx, "fobj", std::max<int64_t>(n, 1), &fobj));
     STCHK(ws(ctx, "changed", k, &changed));
     STCHK(ws(ctx, "obj_partial", nfin + 1, &obj_partial));
-    STCHK(ws(ctx, "objective", 1, &obj));
+    STCHK(ws(ctx, "objective", 2, &obj));
+    const int nobj = ctx->n_cu * 16;   // workgroups of the exact objective (fixed: a fixed summation order)
+    double* obj64_partial = nullptr;
+    if (ctx->opt.exact_objective) STCHK(ws(ctx, "obj64_partial", nobj, &obj64_partial));
 
     WalkArgs A{};
     A.n = n;
@@ -661,7 +537,6 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     A.head = f->H > 0 ? f->head : nullptr;
     A.hval = f->hval;
     A.kpad = (int64_t)f->T * head_ktp(f->kt);
-    A.hbytes = f->H * A.kpad * (f->pdt == SIVF_BF16 ? 2 : 4);
 
     hipStream_t s = ctx->stream;
     HIPCHK(ctx, fill_u64(counters, 0ull, 16 + launches, s));
@@ -683,11 +558,15 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     }
     HIPCHK(ctx, finalize_lambda(k, iter, changed, lambda_out, counters, obj_partial, n > 0 ? nfin : 0, obj, s));
     HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    // the FP64 objective of the new assignment against the centroids it was
+    // made with, F(a^[r], mu^[r-1]) (opt-in; outside the step's timing)
+    if (ctx->opt.exact_objective)
+        HIPCHK(ctx, objective64(A, f->cur, assign_inout, obj64_partial, nobj, obj + 1, s));
     if (stats_host) {
-        unsigned long long c[8];
-        double o = 0.0;
+        unsigned long long c[11];
+        double o[2] = {0.0, 0.0};
         HIPCHK(ctx, hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipMemcpyAsync(&o, obj, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(o, obj, sizeof(o), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
         memset(stats_host, 0, sizeof(*stats_host));
         stats_host->iter = iter;
@@ -698,9 +577,12 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
         stats_host->rescored_candidates = (int64_t)c[4];
         stats_host->moved = (int64_t)c[5];
         stats_host->n_invariant = (int32_t)c[6];
-        stats_host->objective_fast = o;
+        stats_host->objective_fast = o[0];
+        stats_host->objective = ctx->opt.exact_objective ? o[1] : NAN;
         stats_host->head_rows = f->H;
         stats_host->relaxed_objects = (int64_t)c[7];
+        stats_host->walk_bytes = (int64_t)c[10];
+        stats_host->walk_launches = launches;
         float t = 0.0f;
         HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
         stats_host->t_walk_ms = t;
@@ -710,13 +592,9 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     return SIVF_OK;
 }
 
-sivf_status sivf_update(sivf_ctx* ctx, const sivf_csr* X, const int32_t* assign, const uint8_t* lambda,
-                        sivf_ivf* f, sivf_iter_stats* stats_host) {
-    if (!ctx) return SIVF_E_INVALID;
-    DevGuard g(ctx->device);
-    if (!f || !assign || !lambda) return fail(ctx, SIVF_E_INVALID, "NULL argument");
-    Csr Xc;
-    STCHK(validate(ctx, X, &Xc, false));
+// Update step (Alg. 5): centroids from assign, file restructured by lambda.
+sivf_status update_impl(sivf_ctx* ctx, const Csr& Xc, const int32_t* assign, const uint8_t* lambda, sivf_ivf* f,
+                        sivf_iter_stats* stats_host) {
     if (Xc.d != f->d) return fail(ctx, SIVF_E_SHAPE, "X has %lld columns, centroids %lld", (long long)Xc.d, (long long)f->d);
     const int64_t n = Xc.n;
     const int32_t k = f->k;
@@ -765,16 +643,172 @@ sivf_status sivf_update(sivf_ctx* ctx, const sivf_csr* X, const int32_t* assign,
     return SIVF_OK;
 }
 
+}  // namespace
+
+// =========================================================================== ABI
+extern "C" {
+
+sivf_status sivf_default_options(sivf_options* opt) {
+    if (!opt) return SIVF_E_INVALID;
+    opt->posting_dtype = SIVF_F32;
+    opt->filter_mode = SIVF_MODE_SIVF;
+    opt->k_tile = 0;
+    opt->certify = 1;
+    opt->workspace_cap_bytes = 0;
+    opt->head_density = 0.5f;
+    opt->tiles_per_launch = 0;
+    opt->exact_objective = 0;
+    return SIVF_OK;
+}
+
+sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf_options* opt) {
+    if (!out) return SIVF_E_INVALID;
+    *out = nullptr;
+    sivf_options o;
+    sivf_default_options(&o);
+    if (opt) o = *opt;
+    if (o.posting_dtype != SIVF_F32 && o.posting_dtype != SIVF_BF16) return SIVF_E_INVALID;
+    if (o.filter_mode < 0 || o.filter_mode > 3) return SIVF_E_INVALID;
+    if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
+    if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
+    if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
+    if (o.exact_objective != 0 && o.exact_objective != 1) return SIVF_E_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SIVF_E_HIP;
+    sivf_ctx* ctx = new (std::nothrow) sivf_ctx();
+    if (!ctx) return SIVF_E_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->opt = o;
+    DevGuard g(device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        ctx->n_cu = ncu;
+    for (auto& e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete ctx;
+            return SIVF_E_HIP;
+        }
+    }
+    *out = ctx;
+    return SIVF_OK;
+}
+
+sivf_status sivf_destroy(sivf_ctx* ctx) {
+    if (!ctx) return SIVF_OK;
+    DevGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->ws) (void)hipFree(kv.second.first);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return SIVF_OK;
+}
+
+const char* sivf_last_error(const sivf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+sivf_status sivf_validate_csr(sivf_ctx* ctx, const sivf_csr* X) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    Csr c;
+    return validate(ctx, X, &c);
+}
+
+sivf_status sivf_init_centroids(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const int32_t* init_ids_host,
+                                sivf_ivf** out) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!out || !init_ids_host) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc));
+    return init_impl(ctx, Xc, k, init_ids_host, out);
+}
+
+sivf_status sivf_build_centroid_ivf(sivf_ctx* ctx, const sivf_csr* C, const uint8_t* lambda, sivf_ivf** out) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!out) return fail(ctx, SIVF_E_INVALID, "NULL out");
+    return build_impl(ctx, C, lambda, out);
+}
+
+sivf_status sivf_ivf_free(sivf_ctx* ctx, sivf_ivf* ivf) {
+    if (!ivf) return SIVF_OK;
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    free_file(ctx, ivf);
+    return SIVF_OK;
+}
+
+sivf_status sivf_ivf_sizes(sivf_ctx* ctx, const sivf_ivf* f, int32_t* k_host, int64_t* d_host, int64_t* nnz_host,
+                           int32_t* n_tiles_host, int32_t* k_tile_host) {
+    if (!ctx || !f) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (k_host) *k_host = f->k;
+    if (d_host) *d_host = f->d;
+    if (nnz_host) *nnz_host = f->P;
+    if (n_tiles_host) *n_tiles_host = f->T;
+    if (k_tile_host) *k_tile_host = f->kt;
+    return SIVF_OK;
+}
+
+sivf_status sivf_ivf_export(sivf_ctx* ctx, const sivf_ivf* f, int64_t* c_ptr, int32_t* c_col, double* c_val,
+                            uint8_t* lambda, int64_t* term_ptr, int32_t* split, int32_t* p_cid, double* p_val) {
+    if (!ctx || !f) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if ((c_col || c_val) && !c_ptr) return fail(ctx, SIVF_E_INVALID, "c_col/c_val need c_ptr");
+    if ((p_cid || p_val) && !term_ptr) return fail(ctx, SIVF_E_INVALID, "p_cid/p_val need term_ptr");
+    int64_t* sws = nullptr;
+    STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(f->k, f->d) + 1) + 8, &sws));
+    if (c_ptr) {
+        HIPCHK(ctx, exclusive_scan_i64(f->cur.nnz, c_ptr, f->k, sws, ctx->stream));
+        if (c_col || c_val) HIPCHK(ctx, store_export(f->cur, f->k, c_ptr, c_col, c_val, ctx->stream));
+    }
+    if (lambda) HIPCHK(ctx, hipMemcpyAsync(lambda, f->lam, (size_t)f->k, hipMemcpyDeviceToDevice, ctx->stream));
+    if (term_ptr || split) {
+        int64_t* cnt = nullptr;
+        STCHK(ws(ctx, "exp_cnt", f->d, &cnt));
+        HIPCHK(ctx, ivf_export(f, term_ptr, split, p_cid, p_val, cnt, sws, ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SIVF_OK;
+}
+
+sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
+                        float* own_sim_inout, double* own64_inout, uint8_t* lambda_out, sivf_iter_stats* stats_host) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!f || !assign_inout || !own_sim_inout || !lambda_out) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    if (ctx->opt.filter_mode == SIVF_MODE_RELAXED && !own64_inout)
+        return fail(ctx, SIVF_E_INVALID, "the RELAXED filter needs own64_inout");
+    if (iter < 1) return fail(ctx, SIVF_E_INVALID, "iter must be >= 1");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc));
+    return assign_impl(ctx, Xc, f, iter, assign_inout, own_sim_inout, own64_inout, lambda_out, stats_host);
+}
+
+sivf_status sivf_update(sivf_ctx* ctx, const sivf_csr* X, const int32_t* assign, const uint8_t* lambda,
+                        sivf_ivf* f, sivf_iter_stats* stats_host) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!f || !assign || !lambda) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc));
+    return update_impl(ctx, Xc, assign, lambda, f, stats_host);
+}
+
 sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const int32_t* init_ids_host, int32_t max_iter,
                            int32_t* assign_out, float* own_sim_out, sivf_ivf** centroids_out,
                            sivf_iter_stats* per_iter_host, int32_t* iters_done_host) {
     if (!ctx) return SIVF_E_INVALID;
     DevGuard g(ctx->device);
     if (max_iter < 1) return fail(ctx, SIVF_E_INVALID, "max_iter must be >= 1");
+    if (!init_ids_host) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    // X is validated once: the driver holds the stream for the whole run
     Csr Xc;
-    STCHK(validate(ctx, X, &Xc, false));
+    STCHK(validate(ctx, X, &Xc));
     sivf_ivf* f = nullptr;
-    STCHK(sivf_init_centroids(ctx, X, k, init_ids_host, &f));
+    STCHK(init_impl(ctx, Xc, k, init_ids_host, &f));
     int32_t* a = assign_out;
     float* own = own_sim_out;
     uint8_t* lam = nullptr;
@@ -788,13 +822,13 @@ sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const in
     int32_t done = 0;
     for (int32_t r = 1; st == SIVF_OK && r <= max_iter; ++r) {
         sivf_iter_stats stt{};
-        st = sivf_assign(ctx, X, f, r, a, own, own64, lam, &stt);
+        st = assign_impl(ctx, Xc, f, r, a, own, own64, lam, &stt);
         if (st != SIVF_OK) break;
         done = r;
         if (per_iter_host) per_iter_host[r - 1] = stt;
         if (r >= 2 && stt.moved == 0) break;
         if (r == max_iter) break;  // the last assignment's centroids stay as they are
-        st = sivf_update(ctx, X, a, lam, f, &stt);
+        st = update_impl(ctx, Xc, a, lam, f, &stt);
         if (st != SIVF_OK) break;
         if (per_iter_host) per_iter_host[r - 1].t_update_ms = stt.t_update_ms;
     }
@@ -809,6 +843,58 @@ sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const in
     return SIVF_OK;
 }
 
+sivf_status sivf_resume(sivf_ctx* ctx, const sivf_csr* X, const sivf_csr* centroids, const int32_t* a_prev,
+                        const int32_t* a_prev2, sivf_ivf** out, float* own_sim_out, double* own64_out) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!out || !a_prev || !own_sim_out || !centroids) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    if (ctx->opt.filter_mode == SIVF_MODE_RELAXED && !own64_out)
+        return fail(ctx, SIVF_E_INVALID, "the RELAXED filter needs own64_out");
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc));
+    if (centroids->n_cols != Xc.d)
+        return fail(ctx, SIVF_E_SHAPE, "X has %lld columns, centroids %lld", (long long)Xc.d,
+                    (long long)centroids->n_cols);
+    if (centroids->n_rows < 1 || centroids->n_rows > Xc.n)
+        return fail(ctx, SIVF_E_SHAPE, "need 1 <= k <= N (k=%lld, N=%lld)", (long long)centroids->n_rows,
+                    (long long)Xc.n);
+    const int32_t k = (int32_t)centroids->n_rows;
+    STCHK(check_assign(ctx, a_prev, Xc.n, k, "a_prev"));
+    if (a_prev2) STCHK(check_assign(ctx, a_prev2, Xc.n, k, "a_prev2"));
+    // lambda of the restart point: membership of every cluster unchanged
+    // between the last two assignments (all 0 when only one exists)
+    uint8_t *changed = nullptr, *lam = nullptr;
+    unsigned long long* cnt = nullptr;
+    double* dummy = nullptr;
+    STCHK(ws(ctx, "resume_changed", k, &changed));
+    STCHK(ws(ctx, "resume_lam", k, &lam));
+    STCHK(ws(ctx, "resume_cnt", 16, &cnt));
+    STCHK(ws(ctx, "resume_obj", 1, &dummy));
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, fill_u8(changed, 0, k, s));
+    HIPCHK(ctx, fill_u64(cnt, 0ull, 16, s));
+    if (a_prev2 && Xc.n > 0) HIPCHK(ctx, mark_changed(Xc.n, a_prev2, a_prev, changed, s));
+    HIPCHK(ctx, finalize_lambda(k, a_prev2 ? 2 : 1, changed, lam, cnt, nullptr, 0, dummy, s));
+    sivf_ivf* f = nullptr;
+    STCHK(build_impl(ctx, centroids, lam, &f));
+    WalkArgs A{};
+    A.n = Xc.n;
+    A.rp = Xc.rp;
+    A.col = Xc.col;
+    A.xval = Xc.val;
+    A.x_f64 = Xc.f64;
+    if (Xc.n > 0) {
+        hipError_t e = resume_own(A, f->cur, a_prev, f->lam, own_sim_out, own64_out, (int64_t)ctx->n_cu * 16, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            free_file(ctx, f);
+            return fail(ctx, SIVF_E_HIP, "HIP error: %s", hipGetErrorString(e));
+        }
+    }
+    *out = f;
+    return SIVF_OK;
+}
+
 sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr* X, const float* C, int32_t k, float tau, float* lse_out,
                                  double* loss_host) {
     if (!ctx) return SIVF_E_INVALID;
@@ -817,7 +903,7 @@ sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
     if (k < 1) return fail(ctx, SIVF_E_SHAPE, "k must be >= 1");
     if (!(tau > 0.0f) || !std::isfinite(tau)) return fail(ctx, SIVF_E_INVALID, "tau must be positive and finite");
     Csr Xc;
-    STCHK(validate(ctx, X, &Xc, false));
+    STCHK(validate(ctx, X, &Xc));
     if (Xc.f64) return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment takes SIVF_F32 object values");
     float* CT = nullptr;
     double* loss = nullptr;
@@ -842,7 +928,7 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
     if (!(tau > 0.0f) || !std::isfinite(tau)) return fail(ctx, SIVF_E_INVALID, "tau must be positive and finite");
     if (!std::isfinite(grad_loss)) return fail(ctx, SIVF_E_NONFINITE, "grad_loss must be finite");
     Csr Xc;
-    STCHK(validate(ctx, X, &Xc, false));
+    STCHK(validate(ctx, X, &Xc));
     if (Xc.f64) return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment takes SIVF_F32 object values");
     if (!dC_out && !dxval_out) return SIVF_OK;
     const int64_t n = Xc.n, d = Xc.d;

@@ -16,7 +16,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kCandCap = 32;       // candidate-list capacity per object in the fast pass
 constexpr int kTermCap = 128;      // object terms staged in LDS per wave by the fast pass (the rest read from X)
 static_assert(kTermCap % 64 == 0, "the walk reads staged terms a whole 64-term chunk at a time");
-constexpr int64_t kHeadCapBytes = 0xF0000000LL;   // dense head rows beyond this are not built
+constexpr int64_t kHeadMaxBytes = 1LL << 36;      // largest dense head-row buffer a file may request
 constexpr int kWalkWaves = 4;      // waves per workgroup in the walk kernels
 constexpr int kMaxTile = 4096;     // largest similarity tile (centroids) per wave
 
@@ -77,13 +77,13 @@ struct WalkArgs {
     unsigned long long* counters;  // [0] multadds [1] queue len [2] full len [3] icp objects
                                    // [4] re-scored candidates [5] moved [6] invariant
                                    // [7] relaxed-ICP objects [9] own64 queue length
+                                   // [10] bytes requested by the walk's vector loads
                                    // [16 + launch] walk work counters
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)
     const int32_t* head;    // [d] row of each term, -1 if none
     const void* hval;       // [H * kpad] values in the posting dtype
     int64_t kpad;           // row length: T * head_ktp(kt) (each tile padded to 512 slots)
-    int64_t hbytes;         // bytes of hval (< 2^32)
     // relaxed ICP (filter mode RELAXED)
     Store st;                  // the current centroids (FP64 CSR) for exact similarities
     int relaxed;
@@ -135,12 +135,6 @@ struct sivf_ctx {
     int n_cu = 256;
     size_t bytes_held = 0;
     std::map<std::string, std::pair<void*, size_t>> ws;  // grow-only named workspace
-    // identity of the last X that passed validation
-    const void* vx_rp = nullptr;
-    const void* vx_col = nullptr;
-    const void* vx_val = nullptr;
-    int64_t vx_n = -1, vx_d = -1, vx_nnz = -1;
-    int vx_f64 = -1, vx_nonneg = 0;
     hipEvent_t ev[8] = {};
 };
 
@@ -220,6 +214,17 @@ hipError_t finalize_assign(int64_t n, int iter, const int32_t* a_new, const floa
 hipError_t finalize_lambda(int32_t k, int iter, const uint8_t* changed, uint8_t* lam_out,
                            unsigned long long* counters, const double* obj_partial, int nblk,
                            double* obj_out, hipStream_t s);
+// exact FP64 objective sum_i rho(x_i, mu_{a_i}) over the centroids in st, in a
+// fixed order (partial: nblk doubles of workspace)
+hipError_t objective64(const WalkArgs& a, const Store st, const int32_t* assign, double* partial, int nblk,
+                       double* out, hipStream_t s);
+// changed[a_old[i]] = changed[a_new[i]] = 1 where they differ
+hipError_t mark_changed(int64_t n, const int32_t* a_old, const int32_t* a_new, uint8_t* changed, hipStream_t s);
+// restart state: exact FP64 rho of each object to its centroid assign[i] in
+// st; own32 gets it rounded to FP32, own64 (nullable) gets it where the
+// centroid is invariant (lam = 1) and +infinity elsewhere
+hipError_t resume_own(const WalkArgs& a, const Store st, const int32_t* assign, const uint8_t* lam, float* own32,
+                      double* own64, int64_t grid_waves, hipStream_t s);
 
 // update
 struct UpdateWs {

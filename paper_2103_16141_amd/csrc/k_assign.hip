@@ -182,20 +182,38 @@ struct DBatch {
     u32x4 a, b;
 };
 
+// One head row's slots of one tile (ktp values of the posting dtype) as a
+// buffer of its own: offsets inside it stay below 16 KiB, so the rows
+// together may span any number of bytes.
+template <bool BF16>
+__device__ inline __amdgpu_buffer_rsrc_t head_rsrc(const WalkArgs& A, int32_t row, int tile, int ktp) {
+    const int64_t esz = BF16 ? 2 : 4;
+    const char* base = (const char*)A.hval + ((int64_t)row * A.kpad + (int64_t)tile * ktp) * esz;
+    return span_rsrc(base, (int64_t)ktp * esz);
+}
+
+// bytes one wave's vector loads request (64 lanes x width), for the walk's
+// load counter: a list batch (ids + values), a head-row batch, a record
+constexpr uint32_t kListBatchBytes32 = 2 * 256 + 2 * 512;
+constexpr uint32_t kListBatchBytes16 = 2 * 256 + 2 * 256;
+constexpr uint32_t kHeadBatchBytes32 = 2 * 1024;
+constexpr uint32_t kHeadLoadBytes16 = 1024;
+constexpr uint32_t kRecordBytes = 64 * 16;
+
 // FP32 rows: one 512-centroid batch is two 16-byte loads per lane, centroids
-// 4l..4l+3 and 256+4l..256+4l+3 of the batch
-__device__ inline DBatch dense_load32(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
+// 4l..4l+3 and 256+4l..256+4l+3 of the batch; ub is the batch's first slot
+// in the tile
+__device__ inline DBatch dense_load32(__amdgpu_buffer_rsrc_t dd, int ub, int lane) {
     DBatch r;
-    const int so = (int)(uint32_t)(at * 4);
-    r.a = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, so, 0);
-    r.b = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16 + 1024, so, 0);
+    r.a = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, ub * 4, 0);
+    r.b = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16 + 1024, ub * 4, 0);
     return r;
 }
 
 // BF16 rows are stored interleaved per 512-centroid batch: one 16-byte load
 // per lane gives the same two 4-centroid groups (.x .y, then .z .w)
-__device__ inline u32x4 dense_load16(__amdgpu_buffer_rsrc_t dd, int64_t at, int lane) {
-    return __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, (int)(uint32_t)(at * 2), 0);
+__device__ inline u32x4 dense_load16(__amdgpu_buffer_rsrc_t dd, int ub, int lane) {
+    return __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, ub * 2, 0);
 }
 
 __device__ inline void dense_unit32(float* sim, u32x4 w, int c0, float xv) {
@@ -310,11 +328,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     float* cr = (float*)((int32_t*)(lds + kWalkWaves * kts) + kWalkWaves * kCandCap) + wid * kCandCap;
     int32_t* tt = (int32_t*)(lds + kWalkWaves * (kts + 2 * kCandCap)) + wid * kTermCap;
     float* tv = lds + kWalkWaves * (kts + 2 * kCandCap + kTermCap) + wid * kTermCap;
-    const __amdgpu_buffer_rsrc_t dd = span_rsrc(A.hval, A.hbytes);
-
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
     unsigned long long macc = 0, icp_cnt = 0, rel_cnt = 0;
+    uint64_t lbytes = 0;   // bytes requested by this wave's vector loads
+    const uint32_t xb = 4u + (A.x_f64 ? 8u : 4u);   // one staged term: column + value
     constexpr int kGrab = 8;
     for (int64_t g0 = wave_grab(work, kGrab); g0 < A.n; g0 = wave_grab(work, kGrab)) {
         const int64_t gend = min(g0 + kGrab, A.n);
@@ -398,6 +416,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 tt[h] = t;
                 tv[h] = load_xval(A.xval, A.x_f64, r0 + h);
             }
+            lbytes += (uint64_t)min(n, kTermCap) * xb;
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
             const int nch = max(1, (n + 63) >> 6);
@@ -427,6 +446,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 }
                 nrec = A.rec[(int64_t)tl * A.d + (nin ? t : 0)];
                 nv = nin ? xv : 0.0f;
+                lbytes += kRecordBytes + (hb < kTermCap ? 0u : 64u * xb);
             };
             seg_load(0);
             for (int pi = 0; pi < npairs; ++pi) {
@@ -465,26 +485,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const bool use_head = A.head && !(filt && CB);
                 if (use_head && h < n) hrow = hr;
                 unsigned long long dl = ballot(hrow >= 0);
-                const int64_t hb = (int64_t)tile * ktp;   // the tile's slots in a head row
                 if (dl && BF16) {
                     // two terms per pass over the tile (a lone last term is paired
                     // with its own row at weight 0, which adds +-0 exactly)
                     float pa = 0.0f, pb = 0.0f;
-                    int64_t ra = 0, rz = 0;
+                    __amdgpu_buffer_rsrc_t da, db;
                     auto take = [&]() -> bool {
                         if (!dl) return false;
                         int q = __builtin_ctzll(dl);
                         dl &= dl - 1;
                         pa = bcast_f32(v, q);
-                        ra = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        const int32_t row_a = bcast_i32(hrow, q);
+                        int32_t row_b = row_a;
                         pb = 0.0f;
-                        rz = ra;
                         if (dl) {
                             q = __builtin_ctzll(dl);
                             dl &= dl - 1;
                             pb = bcast_f32(v, q);
-                            rz = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                            row_b = bcast_i32(hrow, q);
                         }
+                        da = head_rsrc<BF16>(A, row_a, tile, ktp);
+                        db = head_rsrc<BF16>(A, row_b, tile, ktp);
                         return true;
                     };
                     take();
@@ -495,7 +516,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         ub = 0;
                         return take();
                     };
-                    u32x4 Xa = dense_load16(dd, ra + ub, lane), Xb = dense_load16(dd, rz + ub, lane), Ya, Yb;
+                    u32x4 Xa = dense_load16(da, ub, lane), Xb = dense_load16(db, ub, lane), Ya, Yb;
+                    lbytes += 2 * kHeadLoadBytes16;
                     int xu = ub, yu = 0;
                     float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
                     for (;;) {
@@ -503,8 +525,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
                             break;
                         }
-                        Ya = dense_load16(dd, ra + ub, lane);
-                        Yb = dense_load16(dd, rz + ub, lane);
+                        Ya = dense_load16(da, ub, lane);
+                        Yb = dense_load16(db, ub, lane);
+                        lbytes += 2 * kHeadLoadBytes16;
                         yu = ub;
                         ya = pa;
                         yb = pb;
@@ -513,8 +536,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
                             break;
                         }
-                        Xa = dense_load16(dd, ra + ub, lane);
-                        Xb = dense_load16(dd, rz + ub, lane);
+                        Xa = dense_load16(da, ub, lane);
+                        Xb = dense_load16(db, ub, lane);
+                        lbytes += 2 * kHeadLoadBytes16;
                         xu = ub;
                         xa = pa;
                         xb = pb;
@@ -525,7 +549,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                     dl &= dl - 1;
                     int ub = 0;
                     float xv = bcast_f32(v, q);
-                    int64_t rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                    __amdgpu_buffer_rsrc_t dr = head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp);
                     auto dadv = [&]() -> bool {
                         ub += 512;
                         if (ub < dlim) return true;
@@ -534,10 +558,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         dl &= dl - 1;
                         ub = 0;
                         xv = bcast_f32(v, q);
-                        rb = (int64_t)bcast_i32(hrow, q) * A.kpad + hb;
+                        dr = head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp);
                         return true;
                     };
-                    DBatch X = dense_load32(dd, rb + ub, lane), Y;
+                    DBatch X = dense_load32(dr, ub, lane), Y;
+                    lbytes += kHeadBatchBytes32;
                     int xu = ub, yu = 0;
                     float xx = xv, yx = 0.0f;
                     for (;;) {
@@ -545,7 +570,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate32(sim, X, xu, A.kt, xx, lane);
                             break;
                         }
-                        Y = dense_load32(dd, rb + ub, lane);
+                        Y = dense_load32(dr, ub, lane);
+                        lbytes += kHeadBatchBytes32;
                         yu = ub;
                         yx = xv;
                         dense_accumulate32(sim, X, xu, A.kt, xx, lane);
@@ -553,7 +579,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
                             break;
                         }
-                        X = dense_load32(dd, rb + ub, lane);
+                        X = dense_load32(dr, ub, lane);
+                        lbytes += kHeadBatchBytes32;
                         xu = ub;
                         xx = xv;
                         dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
@@ -586,7 +613,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         return true;
                     };
                     next_list();
+                    constexpr uint32_t lbb = BF16 ? kListBatchBytes16 : kListBatchBytes32;
                     Batch X = load_batch<BF16>(dc, dv, off, lane), Y;
+                    lbytes += lbb;
                     int xs = lo - off, xe = hi - off, ys = 0, ye = 0;
                     float xv = lv, yv = 0.0f;
                     off += kBatch;
@@ -596,6 +625,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             break;
                         }
                         Y = load_batch<BF16>(dc, dv, off, lane);
+                        lbytes += lbb;
                         ys = lo - off;
                         ye = hi - off;
                         yv = lv;
@@ -606,6 +636,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             break;
                         }
                         X = load_batch<BF16>(dc, dv, off, lane);
+                        lbytes += lbb;
                         xs = lo - off;
                         xe = hi - off;
                         xv = lv;
@@ -763,6 +794,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     macc = (unsigned long long)wave_sum_i64((int64_t)macc);
     if (lane == 0) {
         atomicAdd(&A.counters[0], macc);
+        atomicAdd(&A.counters[10], (unsigned long long)lbytes);
         atomicAdd(&A.counters[3], icp_cnt);
         if (rel_cnt) atomicAdd(&A.counters[7], rel_cnt);
     }
@@ -1052,6 +1084,100 @@ hipError_t own64_update(const WalkArgs& a, double* own64, int32_t* queue, int64_
     int64_t blocks = (grid_waves + 3) / 4;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_own64_exact, dim3((unsigned)blocks), dim3(256), 0, s, a, own64, queue);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact FP64 objective F(a, mu) = sum_i rho(x_i, mu_{a_i}) (the spherical
+// k-means objective of Section 1): each rho is exact_rho's fold (the
+// reference order), summed in a fixed order -- every wave adds its objects in
+// ascending id, the workgroup adds its waves in order, one thread adds the
+// workgroups in order -- so the value is run-to-run identical for a fixed grid.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_objective64(WalkArgs A, Store st, const int32_t* __restrict__ assign,
+                                                     double* __restrict__ partial) {
+    __shared__ double sh[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    double acc = 0.0;
+    for (int64_t i = wave; i < A.n; i += nw) {
+        const int64_t r0 = A.rp[i];
+        const double r = exact_rho(A, st, r0, (int)(A.rp[i + 1] - r0), assign[i]);
+        acc = acc + r;
+    }
+    if (lane == 0) sh[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t = t + partial[b];
+    *out = t;
+}
+
+hipError_t objective64(const WalkArgs& a, const Store st, const int32_t* assign, double* partial, int nblk,
+                       double* out, hipStream_t s) {
+    if (a.n > 0) {
+        hipLaunchKernelGGL(k_objective64, dim3((unsigned)nblk), dim3(256), 0, s, a, st, assign, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else {
+        nblk = 0;
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partial, nblk, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Restart helpers: the clusters whose membership changed between two
+// assignments (Alg. 4, marking invariant clusters), and the exact own
+// similarities a restarted assignment step starts the ICP branch from.
+// ---------------------------------------------------------------------------
+__global__ void k_mark_changed(int64_t n, const int32_t* __restrict__ a_old, const int32_t* __restrict__ a_new,
+                               uint8_t* __restrict__ changed) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t ao = a_old[i], an = a_new[i];
+        if (ao != an) {
+            changed[ao] = 1;
+            changed[an] = 1;
+        }
+    }
+}
+
+hipError_t mark_changed(int64_t n, const int32_t* a_old, const int32_t* a_new, uint8_t* changed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_mark_changed, dim3((unsigned)blocks), dim3(256), 0, s, n, a_old, a_new, changed);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_resume_own(WalkArgs A, Store st, const int32_t* __restrict__ assign,
+                                                    const uint8_t* __restrict__ lam, float* __restrict__ own32,
+                                                    double* __restrict__ own64) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < A.n; i += nw) {
+        const int64_t r0 = A.rp[i];
+        const int32_t j = assign[i];
+        const double r = exact_rho(A, st, r0, (int)(A.rp[i + 1] - r0), j);
+        if (lane == 0) {
+            own32[i] = (float)r;
+            if (own64) own64[i] = lam[j] ? r : INFINITY;
+        }
+    }
+}
+
+hipError_t resume_own(const WalkArgs& a, const Store st, const int32_t* assign, const uint8_t* lam, float* own32,
+                      double* own64, int64_t grid_waves, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    int64_t blocks = (grid_waves + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_resume_own, dim3((unsigned)blocks), dim3(256), 0, s, a, st, assign, lam, own32, own64);
     return hipGetLastError();
 }
 

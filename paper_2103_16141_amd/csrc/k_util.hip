@@ -120,42 +120,95 @@ hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_
 //           bit2 non-finite value, bit3 row_ptr inconsistent with nnz
 // flags[1]: smallest offending row (initialised to ~0 by the host)
 // flags[2]: 1 if some value is negative
-__global__ void k_validate(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           const void* __restrict__ val, int f64, int64_t n, int64_t d, int64_t nnz,
-                           unsigned long long* flags) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t b = rp[i], e = rp[i + 1];
+//
+// One wave per group of 64 consecutive rows: lane l holds the bounds of row
+// g*64 + l, and the wave reads the group's nonzeros as one contiguous range,
+// 64 at a time (coalesced).  For each such window the lanes OR together the
+// bits of the row starts that fall in it, so a lane knows whether its element
+// opens a row; otherwise its column must exceed its left neighbour's (taken
+// by a shuffle, lane 0 from the previous window).  Row bounds that are out of
+// order are reported as such and their group's elements are not inspected.
+__device__ inline unsigned long long wave_or_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_validate(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const void* __restrict__ val, int f64, int64_t n, int64_t d,
+                                                  int64_t nnz, unsigned long long* flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t ngroups = (n + 63) / 64;
+    for (int64_t g = wave; g < ngroups; g += nw) {
+        const int64_t i = g * 64 + lane;
+        const bool row = i < n;
+        int64_t b = 0, e = 0;
         unsigned long long bad = 0;
+        if (row) {
+            b = rp[i];
+            e = rp[i + 1];
+            if (i == 0 && b != 0) bad |= 8;
+            if (i == n - 1 && e != nnz) bad |= 8;
+            if (e < b || b < 0 || e > nnz) bad |= 1;
+        }
+        int64_t first_bad_row = bad ? i : INT64_MAX;
+        const bool bounds_ok = ballot(bad != 0) == 0ull;
+        unsigned long long ebad = 0;
         int neg = 0;
-        if (i == 0 && b != 0) bad |= 8;
-        if (i == n - 1 && e != nnz) bad |= 8;
-        if (e < b || b < 0 || e > nnz) {
-            bad |= 1;
-        } else {
-            int32_t last = -1;
-            for (int64_t p = b; p < e; ++p) {
-                int32_t c = col[p];
-                if (c < 0 || c >= d) bad |= 2;
-                if (c <= last) bad |= 1;
-                last = c;
-                double v = f64 ? ((const double*)val)[p] : (double)((const float*)val)[p];
-                if (!isfinite(v)) bad |= 4;
-                if (v < 0) neg = 1;
+        if (bounds_ok) {
+            // the group's nonzeros: [rp[g*64], rp[min(g*64+64, n)])
+            const int64_t lo = bcast_i64(b, 0);
+            const int last_lane = (int)min<int64_t>(63, n - 1 - g * 64);
+            const int64_t hi = bcast_i64(e, last_lane);
+            int32_t prev_last = -1;
+            for (int64_t q = lo; q < hi; q += 64) {
+                // rows (non-empty) starting inside [q, q + 64)
+                const unsigned long long sb =
+                    (row && b < e && b >= q && b < q + 64) ? (1ull << (int)(b - q)) : 0ull;
+                const unsigned long long starts = wave_or_u64(sb);
+                const int64_t p = q + lane;
+                const bool in = p < hi;
+                int32_t c = in ? col[p] : 0;
+                int32_t left = __shfl_up(c, 1, 64);
+                if (lane == 0) left = prev_last;
+                unsigned long long eb = 0;
+                if (in) {
+                    if (c < 0 || c >= d) eb |= 2;
+                    if (!((starts >> lane) & 1ull) && c <= left) eb |= 1;
+                    const double v = f64 ? ((const double*)val)[p] : (double)((const float*)val)[p];
+                    if (!isfinite(v)) eb |= 4;
+                    if (v < 0) neg = 1;
+                }
+                prev_last = __shfl(c, 63, 64);
+                if (ballot(eb != 0)) {
+                    // error path: the row of each offending element (the last
+                    // row of the group starting at or before it)
+                    int64_t rbad = INT64_MAX;
+                    for (int l = 0; l < 64 && g * 64 + l < n; ++l) {
+                        const int64_t bl = bcast_i64(b, l), el = bcast_i64(e, l);
+                        if (eb && p >= bl && p < el) rbad = g * 64 + l;
+                    }
+                    first_bad_row = min(first_bad_row, rbad);
+                    ebad |= eb;
+                }
             }
         }
+        bad |= ebad;
         if (bad) {
             atomicOr(&flags[0], bad);
-            atomicMin(&flags[1], (unsigned long long)i);
+            atomicMin(&flags[1], (unsigned long long)first_bad_row);
         }
-        if (neg) atomicOr(&flags[2], 1ull);
+        if (ballot(neg != 0) && lane == 0) atomicOr(&flags[2], 1ull);
     }
 }
 
 hipError_t validate_csr(const int64_t* rp, const int32_t* col, const void* val, int f64, int64_t n, int64_t d,
                         int64_t nnz, unsigned long long* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
+    int64_t blocks = ((n + 63) / 64 + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, s, rp, col, val, f64, n, d, nnz, flags);
     return hipGetLastError();
 }

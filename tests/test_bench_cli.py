@@ -27,7 +27,7 @@ def test_walk_hash_prints():
 
 
 def test_traffic_profile_used_only_for_matching_sources(tmp_path, monkeypatch):
-    # The stored HBM-traffic figure is reported only while the walk sources
+    # The stored DRAM-traffic record is reported only while the walk sources
     # hash as they did when the counters were taken; else it is null.
     sys.path.insert(0, ROOT)
     try:
@@ -38,9 +38,26 @@ def test_traffic_profile_used_only_for_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "traffic.md"
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
     assert bench.measured_traffic() is None                      # no profile
-    prof.write_text('text\nTRAFFIC_JSON {"walk_source_hash": "%s", "hbm_bytes_per_launch": 123.5}\n' % h)
-    assert bench.measured_traffic() == 123.5
-    prof.write_text('TRAFFIC_JSON {"walk_source_hash": "0000000000000000", "hbm_bytes_per_launch": 123.5}\n')
+    prof.write_text('text\nTRAFFIC_JSON {"walk_source_hash": "%s", "dram_bytes_per_launch": 123.5, '
+                    '"launch_ms": 2.0}\n' % h)
+    assert bench.measured_traffic()["dram_bytes_per_launch"] == 123.5
+    prof.write_text('TRAFFIC_JSON {"walk_source_hash": "0000000000000000", "dram_bytes_per_launch": 123.5}\n')
     assert bench.measured_traffic() is None                      # taken on other kernel sources
     prof.write_text('TRAFFIC_JSON {not json}\n')
     assert bench.measured_traffic() is None
+
+
+def test_probe_cases_stay_inside_their_buffer():
+    # every probe window starts below its region and the buffer holds
+    # region + window bytes, so no load leaves the allocation
+    sys.path.insert(0, ROOT)
+    try:
+        import bench
+    finally:
+        sys.path.remove(ROOT)
+    need = max(c[3] + c[4] for c in bench.PROBE_CASES)
+    for name, kind, width, region, window, stride in bench.PROBE_CASES:
+        if kind:
+            continue
+        assert window >= 256 * width * 4, name          # one round of a workgroup fits the window
+        assert region + window <= need and region < 2 ** 32 and window < 2 ** 31, name

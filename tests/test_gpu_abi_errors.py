@@ -143,3 +143,80 @@ def test_empty_matrix_and_zero_rows():
     X = _X(c)
     a, own, ivf, stats = ctx.run_lloyd(X, 2, [0, 1], 3)
     assert a.cpu().tolist() == [0, 1] and stats[-1]["moved"] == 0
+
+
+def test_in_place_edits_are_validated_again():
+    """X edited in place (same pointers, same sizes) after a successful call
+    is checked again before any kernel indexes with it: an out-of-range
+    column is rejected with the outputs untouched, and values whose sign
+    changed switch the certificate to the signed-data bound, so the next
+    assignment still equals the oracle's."""
+    import oracle
+    log("abi: in-place edits of a validated X")
+    ctx = _ctx(k_tile=64)
+    c = synth.make_corpus(3000, 600, 20, 1.0, np.float32, seed=9)
+    X = _X(c)
+    k = 70
+    ids = synth.init_ids(c.n, k, 19)
+    ivf = ctx.init_centroids(X, k, ids)
+    a = torch.zeros(c.n, dtype=torch.int32, device=device())
+    own = torch.zeros(c.n, dtype=torch.float32, device=device())
+    lam = torch.zeros(k, dtype=torch.uint8, device=device())
+    ctx.assign(X, ivf, 1, a, own, lam)
+    a_ok = a.clone()
+    # an out-of-range column written into the validated X
+    p = int(c.row_ptr[1234 + 1] - 1)        # last entry of a row: still ascending
+    saved = int(X.col[p])
+    X.col[p] = c.d + 7
+    a.fill_(3)
+    assert _status(lambda: ctx.assign(X, ivf, 1, a, own, lam)) == "SIVF_E_RANGE"
+    assert bool((a == 3).all())
+    assert _status(lambda: ctx.update(X, a_ok, lam, ivf)) == "SIVF_E_RANGE"
+    X.col[p] = saved
+    # a duplicate column (unsorted row) written in place
+    q = int(np.nonzero(np.diff(c.row_ptr) >= 3)[0][5])
+    b0 = int(c.row_ptr[q])
+    saved = int(X.col[b0 + 1])
+    X.col[b0 + 1] = X.col[b0]
+    assert _status(lambda: ctx.assign(X, ivf, 1, a, own, lam)) == "SIVF_E_UNSORTED"
+    X.col[b0 + 1] = saved
+    # signs flipped in place: the same file (nonnegative centroids) against
+    # signed objects must use the absolute bound
+    flip = torch.from_numpy(np.random.default_rng(4).random(c.nnz) < 0.35).to(device())
+    X.val[flip] = -X.val[flip]
+    ctx.assign(X, ivf, 1, a, own, lam)
+    signed = synth.Corpus(c.n, c.d, c.row_ptr, c.col, X.val.cpu().numpy())
+    ref, _, _ = oracle.assign(signed, oracle.init_centroids(c, ids))
+    assert np.array_equal(a.cpu().numpy(), ref)
+
+
+def test_validation_errors_at_group_edges():
+    """The validator reads 64 rows per wave; errors in the first and last row
+    of such a group, across a group boundary, and in the last row of X are all
+    found and name their row."""
+    log("abi: validation at row-group edges")
+    ctx = _ctx()
+    base = synth.make_corpus(300, 400, 9, 1.0, np.float32, seed=12)
+    for row in (0, 63, 64, 127, 128, 299):
+        for kind in ("range", "unsorted", "nan"):
+            c = synth.Corpus(base.n, base.d, base.row_ptr, base.col.copy(), base.val.copy())
+            b, e = int(c.row_ptr[row]), int(c.row_ptr[row + 1])
+            assert e - b >= 2
+            if kind == "range":
+                c.col[e - 1] = c.d
+            elif kind == "unsorted":
+                c.col[b + 1] = c.col[b]
+            else:
+                c.val[b] = np.inf
+            want = {"range": "SIVF_E_RANGE", "unsorted": "SIVF_E_UNSORTED", "nan": "SIVF_E_NONFINITE"}[kind]
+            from paper_2103_16141_amd._native import SivfError
+            with pytest.raises(SivfError) as err:
+                ctx.validate(_X(c))
+            assert err.value.name == want, (row, kind)
+            assert ("row %d " % row) in str(err.value), (row, kind, str(err.value))
+    # a row whose first column is below the previous row's last column is fine
+    ctx.validate(_X(base))
+    # row_ptr decreasing inside a group
+    c = synth.Corpus(base.n, base.d, base.row_ptr.copy(), base.col, base.val)
+    c.row_ptr[70] = c.row_ptr[71] + 1
+    assert _status(lambda: ctx.validate(_X(c))) == "SIVF_E_UNSORTED"

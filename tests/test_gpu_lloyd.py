@@ -335,3 +335,21 @@ def test_flag_patterns_on_a_built_file(posting, mode, tiles_per_launch, signed):
         assert st["icp_objects"] == int(lam[a0].astype(bool).sum()), name
         ivf.free()
     ctx.close()
+
+
+@pytest.mark.parametrize("posting", ["fp32", "bf16"])
+def test_every_term_dense(posting):
+    """Full-expression centroids (the paper's Lloyd-ICP baseline, Section 3.1
+    and Section 5): with head_density near 0 every term held by any centroid
+    gets a dense row, so the walk multiplies objects against dense centroids
+    and reads no structured list; ICP objects read the moving prefix of each
+    row.  Same trajectory and counts as the structured file."""
+    log("every term dense, %s postings" % posting)
+    c = synth.make_corpus(4000, 1500, 30, 1.0, np.float32, seed=141)
+    ids = synth.init_ids(4000, 150, 41)
+    tr, st = lloyd_parity(_ctx(k_tile=64, posting_dtype=posting, head_density=1e-6), _X(c), c, 150, ids, 8)
+    used = np.unique(c.col).size
+    assert st[0]["head_rows"] == np.unique(np.concatenate(
+        [c.col[c.row_ptr[i]:c.row_ptr[i + 1]] for i in ids])).size
+    assert all(0 < s["head_rows"] <= used for s in st)
+    assert sum(s["icp_objects"] for s in st) > 0

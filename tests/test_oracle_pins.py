@@ -258,6 +258,64 @@ def test_objective_monotone(seed):
 
 
 # --------------------------------------------------------------------------
+# restart between iterations (Alg. 1): the state after an update is the
+# centroids and the last two assignments; continuing from it must reproduce
+# the uninterrupted run bitwise (assignments, cached own similarities, flags,
+# counts, centroids)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("r_done", [1, 2, 5])
+def test_resume_reproduces_the_trajectory(r_done):
+    c = synth.make_corpus(1200, 300, 14, 1.0, np.float64, seed=21)
+    ids = synth.init_ids(1200, 30, 22)
+    full = oracle.lloyd(c, 30, ids, 12, icp=True, keep_centroids=True)
+    assert full.iters > r_done + 2
+    cents = full.centroids[r_done]          # mu^[r_done]: what assignment r_done + 1 reads
+    a2 = full.assign[r_done - 2] if r_done >= 2 else None
+    st = oracle.resume_state(c, cents, full.assign[r_done - 1], a2)
+    assert np.array_equal(st.lam, full.lam[r_done - 1])
+    # own similarities of the ICP objects equal the cached ones bitwise
+    # (their centroid did not move, and the fold is the assignment's)
+    icp = st.lam[st.a] == 1
+    assert np.array_equal(st.own[icp].view(np.uint64), full.own[r_done - 1][icp].view(np.uint64))
+    st.r = r_done
+    res = oracle.lloyd(c, 30, None, 12, icp=True, keep_centroids=True, start=st)
+    assert res.iters == full.iters and len(res.assign) == full.iters - r_done
+    for q, r in enumerate(range(r_done + 1, full.iters + 1)):
+        assert np.array_equal(res.assign[q], full.assign[r - 1]), r
+        assert np.array_equal(res.own[q].view(np.uint64), full.own[r - 1].view(np.uint64)), r
+        assert np.array_equal(res.lam[q], full.lam[r - 1]), r
+        assert res.multadds[q] == full.multadds[r - 1], r
+        assert res.moved[q] == full.moved[r - 1], r
+    assert np.array_equal(res.final.val.view(np.uint64), full.final.val.view(np.uint64))
+
+
+def test_resume_without_flags_is_not_a_restart():
+    """A restart that forgets the flags (treats every cluster as moving) still
+    gives the same assignments -- the ICP filter only skips comparisons -- but
+    more mult-adds: the counts pin that the flags are part of the state."""
+    c = synth.make_corpus(1200, 300, 14, 1.0, np.float64, seed=23)
+    ids = synth.init_ids(1200, 30, 24)
+    full = oracle.lloyd(c, 30, ids, 10, icp=True, keep_centroids=True)
+    r_done = 4
+    st = oracle.resume_state(c, full.centroids[r_done], full.assign[r_done - 1], full.assign[r_done - 2])
+    assert st.lam.sum() > 0
+    st.lam = np.zeros_like(st.lam)
+    st.r = r_done
+    res = oracle.lloyd(c, 30, None, r_done + 1, icp=True, start=st)
+    assert np.array_equal(res.assign[0], full.assign[r_done])
+    assert res.multadds[0] > full.multadds[r_done]
+
+
+def test_relaxed_icp_cannot_resume():
+    c = synth.make_corpus(200, 50, 6, 1.0, np.float64, seed=25)
+    ids = synth.init_ids(200, 5, 26)
+    full = oracle.lloyd(c, 5, ids, 3, icp=True, keep_centroids=True)
+    st = oracle.resume_state(c, full.centroids[2], full.assign[1], full.assign[0])
+    with pytest.raises(ValueError):
+        oracle.lloyd(c, 5, None, 5, icp=True, relaxed=True, start=st)
+
+
+# --------------------------------------------------------------------------
 # structured inverted file (Section 4, Alg. 5)
 # --------------------------------------------------------------------------
 def test_ivf_layout_and_roundtrip():
