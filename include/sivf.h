@@ -241,6 +241,22 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* ivf, i
                         int32_t* assign_inout, float* own_sim_inout, double* own64_inout, uint8_t* lambda_out,
                         sivf_iter_stats* stats_host);
 
+/* sivf_assign for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step with the same arguments, results and errors, but its
+ * workspace is a fixed 64 MiB block per device that the library holds from
+ * its first use on the device until the process ends; the call makes no
+ * device allocation and frees nothing.  The block bounds the sizes it takes:
+ * about 330 bytes per object for k above one tile, 50 otherwise (so some
+ * 190,000 objects against a multi-tile file); a larger request returns
+ * SIVF_E_UNSUPPORTED before anything is written.  Every call on a device
+ * shares that device's block and each call initialises what it reads, so
+ * consecutive calls are independent; calls that overlap in time on one device
+ * (several ctxs or streams) race on the block and must not be issued. */
+sivf_status sivf_assign_noalloc(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* ivf, int32_t iter,
+                                int32_t* assign_inout, float* own_sim_inout, double* own64_inout,
+                                uint8_t* lambda_out, sivf_iter_stats* stats_host);
+
 /* Update step r (Alg. 5): replace the file's centroids by mu^[r] computed from
  * X and assign = a^[r] (int32[N], values in [0, k)), and restructure it with
  * lambda = lambda^[r] (uint8[k]).  Clusters with lambda_j = 1 or no members keep

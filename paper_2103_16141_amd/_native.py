@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
         "sivf_ivf_sizes": ([vp, vp, P(i32), P(i64), P(i64), P(i32), P(i32)], st),
         "sivf_ivf_export": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], st),
         "sivf_assign": ([vp, csr_p, vp, i32, vp, vp, vp, vp, stats_p], st),
+        "sivf_assign_noalloc": ([vp, csr_p, vp, i32, vp, vp, vp, vp, stats_p], st),
         "sivf_update": ([vp, csr_p, vp, vp, vp, stats_p], st),
         "sivf_run_lloyd": ([vp, csr_p, i32, vp, i32, vp, vp, P(vp), stats_p, P(i32)], st),
         "sivf_resume": ([vp, csr_p, csr_p, vp, vp, P(vp), vp, vp], st),

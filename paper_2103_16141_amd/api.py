@@ -185,6 +185,14 @@ class Context:
                                        _ptr(own64), _ptr(lam_out), ctypes.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
+    def assign_noalloc(self, X: DeviceCsr, ivf: Ivf, it: int, a, own, lam_out, stats=True, own64=None):
+        """assign() through the entry point that allocates no device memory."""
+        s = X.struct()
+        st = N.sivf_iter_stats()
+        self._chk(N.load().sivf_assign_noalloc(self.handle, ctypes.byref(s), ivf.handle, int(it), _ptr(a), _ptr(own),
+                                               _ptr(own64), _ptr(lam_out), ctypes.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
     def update(self, X: DeviceCsr, a, lam, ivf: Ivf, stats=True):
         s = X.struct()
         st = N.sivf_iter_stats()

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -106,6 +107,63 @@ sivf_status ws(sivf_ctx* ctx, const char* name, int64_t elems, T** out) {
     return SIVF_OK;
 }
 
+// Workspace of one call, handed out buffer by buffer: the ctx's grow-only
+// named buffers (kCtx), consecutive 256-byte aligned pieces of a fixed device
+// block that is never allocated or freed here (kFixed), or no memory at all,
+// only the byte count such a block needs for the same requests (kMeasure).
+struct Work {
+    enum Mode { kCtx, kFixed, kMeasure };
+    sivf_ctx* ctx;
+    Mode mode = kCtx;
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+
+    template <typename T>
+    sivf_status get(const char* name, int64_t elems, T** out) {
+        if (mode == kCtx) return ws(ctx, name, elems, out);
+        const size_t bytes = (size_t)std::max<int64_t>(elems, 1) * sizeof(T);
+        const size_t at = (used + 255) & ~(size_t)255;
+        if (mode == kFixed && at + bytes > cap)
+            return fail(ctx, SIVF_E_UNSUPPORTED, "workspace '%s' does not fit the %zu-byte scratch block", name, cap);
+        *out = (T*)(base + at);   // kMeasure: an offset, never dereferenced
+        used = at + bytes;
+        return SIVF_OK;
+    }
+};
+
+// ------------------------------------------------------------ fixed scratch
+// The workspace of sivf_assign_noalloc: one block per device, part of the
+// library's device code, so the loader provides it when the library is first
+// used on a device and it stays until the process ends.  Host code never
+// names the array itself (that is a host-side stand-in, not a device
+// address): it uses the address hipGetSymbolAddress reports for each device,
+// taken once per device with that device current, when a ctx is created.
+constexpr size_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device must be current
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 sivf_status check_csr_args(sivf_ctx* ctx, const sivf_csr* X, const char* what) {
     if (!X) return fail(ctx, SIVF_E_INVALID, "%s is NULL", what);
     if (X->n_rows < 0 || X->n_cols < 1 || X->nnz < 0)
@@ -124,11 +182,11 @@ sivf_status check_csr_args(sivf_ctx* ctx, const sivf_csr* X, const char* what) {
 // both the column range (used as an index by the walk) and the sign of the
 // values (which selects the certificate's error bound) must hold for the
 // contents the kernels will read.  One coalesced pass over the nonzeros.
-sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out) {
+sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out, Work& w) {
     STCHK(check_csr_args(ctx, X, "X"));
     const int f64 = X->val_dtype == SIVF_F64;
     unsigned long long* flags = nullptr;
-    STCHK(ws(ctx, "vflags", 4, &flags));
+    STCHK(w.get("vflags", 4, &flags));
     unsigned long long init[3] = {0ull, ~0ull, 0ull};
     HIPCHK(ctx, hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
     if (X->n_rows > 0)
@@ -156,11 +214,16 @@ sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out) {
     return SIVF_OK;
 }
 
+sivf_status validate(sivf_ctx* ctx, const sivf_csr* X, Csr* out) {
+    Work w{ctx};
+    return validate(ctx, X, out, w);
+}
+
 // Every a[i] must lie in [0, k) before it is used as an index on the device.
-sivf_status check_assign(sivf_ctx* ctx, const int32_t* a, int64_t n, int32_t k, const char* what) {
-    if (n <= 0) return SIVF_OK;
+sivf_status check_assign(sivf_ctx* ctx, const int32_t* a, int64_t n, int32_t k, const char* what, Work& w) {
     unsigned long long* flags = nullptr;
-    STCHK(ws(ctx, "aflags", 2, &flags));
+    STCHK(w.get("aflags", 2, &flags));
+    if (n <= 0) return SIVF_OK;
     HIPCHK(ctx, fill_u64(flags, 0ull, 1, ctx->stream));
     HIPCHK(ctx, range_check_i32(a, n, k, flags, ctx->stream));
     unsigned long long h = 0;
@@ -168,6 +231,11 @@ sivf_status check_assign(sivf_ctx* ctx, const int32_t* a, int64_t n, int32_t k, 
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (h) return fail(ctx, SIVF_E_RANGE, "%s has a value outside [0, %d)", what, k);
     return SIVF_OK;
+}
+
+sivf_status check_assign(sivf_ctx* ctx, const int32_t* a, int64_t n, int32_t k, const char* what) {
+    Work w{ctx};
+    return check_assign(ctx, a, n, k, what, w);
 }
 
 void choose_tiles(const sivf_ctx* ctx, int32_t k, int32_t* kt, int32_t* T) {
@@ -443,37 +511,76 @@ sivf_status build_impl(sivf_ctx* ctx, const sivf_csr* C, const uint8_t* lambda, 
     return SIVF_OK;
 }
 
+// The assignment step's workspace (everything it reads or writes besides
+// its inputs, outputs and the file).
+struct AssignBufs {
+    unsigned long long* counters = nullptr;
+    int32_t *a_new = nullptr, *qobj = nullptr, *qcand = nullptr, *qcnt = nullptr, *fobj = nullptr;
+    float* own_new = nullptr;
+    uint8_t* changed = nullptr;
+    double *obj_partial = nullptr, *obj = nullptr, *obj64_partial = nullptr;
+    double *st_theta = nullptr, *st_best = nullptr, *own64_cur = nullptr;
+    int32_t *st_bj = nullptr, *st_cnt = nullptr, *st_cj = nullptr, *own64_queue = nullptr;
+    float* st_cr = nullptr;
+    uint8_t* st_rel = nullptr;
+    int64_t qcap = 0;
+    int nfin = 0, launches = 0, tpl = 0, nobj = 0;
+};
+
+sivf_status assign_buffers(sivf_ctx* ctx, Work& w, int64_t n, int32_t k, int32_t T, AssignBufs* b) {
+    const int relaxed = ctx->opt.filter_mode == SIVF_MODE_RELAXED;
+    b->qcap = std::max<int64_t>(1024, n / 4);
+    b->nfin = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
+    b->tpl = std::min<int>(T, std::max<int>(1, ctx->opt.tiles_per_launch));
+    b->launches = (T + b->tpl - 1) / b->tpl;
+    b->nobj = ctx->n_cu * 16;   // workgroups of the exact objective (fixed: a fixed summation order)
+    STCHK(w.get("counters", 16 + b->launches, &b->counters));
+    STCHK(w.get("a_new", n, &b->a_new));
+    STCHK(w.get("own_new", n, &b->own_new));
+    STCHK(w.get("qobj", b->qcap, &b->qobj));
+    STCHK(w.get("qcand", b->qcap * kCandCap, &b->qcand));
+    STCHK(w.get("qcnt", b->qcap, &b->qcnt));
+    STCHK(w.get("fobj", std::max<int64_t>(n, 1), &b->fobj));
+    STCHK(w.get("changed", k, &b->changed));
+    STCHK(w.get("obj_partial", b->nfin + 1, &b->obj_partial));
+    STCHK(w.get("objective", 2, &b->obj));
+    if (ctx->opt.exact_objective) STCHK(w.get("obj64_partial", b->nobj, &b->obj64_partial));
+    const int64_t m = std::max<int64_t>(n, 1);
+    if (b->launches > 1) {
+        STCHK(w.get("st_theta", m, &b->st_theta));
+        STCHK(w.get("st_best", m, &b->st_best));
+        STCHK(w.get("st_bj", m, &b->st_bj));
+        STCHK(w.get("st_cnt", m, &b->st_cnt));
+        STCHK(w.get("st_cj", m * kCandCap, &b->st_cj));
+        STCHK(w.get("st_cr", m * kCandCap, &b->st_cr));
+    }
+    if (relaxed) {
+        STCHK(w.get("own64_cur", m, &b->own64_cur));
+        STCHK(w.get("own64_queue", m, &b->own64_queue));
+        if (b->launches > 1) STCHK(w.get("st_rel", m, &b->st_rel));
+    }
+    return SIVF_OK;
+}
+
 // Assignment step r = iter (Alg. 4) of X against the file f.
-sivf_status assign_impl(sivf_ctx* ctx, const Csr& Xc, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
+sivf_status assign_impl(sivf_ctx* ctx, Work& w, const Csr& Xc, const sivf_ivf* f, int32_t iter, int32_t* assign_inout,
                         float* own_sim_inout, double* own64_inout, uint8_t* lambda_out, sivf_iter_stats* stats_host) {
     if (Xc.d != f->d) return fail(ctx, SIVF_E_SHAPE, "X has %lld columns, centroids %lld", (long long)Xc.d, (long long)f->d);
     const int64_t n = Xc.n;
     const int32_t k = f->k;
     const int relaxed = ctx->opt.filter_mode == SIVF_MODE_RELAXED;
     const int icp_on = iter >= 2 && ctx->opt.filter_mode != SIVF_MODE_IVF;
-    if (iter >= 2) STCHK(check_assign(ctx, assign_inout, n, k, "assign_inout (a^[r-1])"));
-    const int64_t qcap = std::max<int64_t>(1024, n / 4);
-    unsigned long long* counters = nullptr;
-    int32_t *a_new = nullptr, *qobj = nullptr, *qcand = nullptr, *qcnt = nullptr, *fobj = nullptr;
-    float* own_new = nullptr;
-    uint8_t* changed = nullptr;
-    double *obj_partial = nullptr, *obj = nullptr;
-    const int nfin = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
-    const int tpl = std::min<int>(f->T, std::max<int>(1, ctx->opt.tiles_per_launch));
-    const int launches = (f->T + tpl - 1) / tpl;
-    STCHK(ws(ctx, "counters", 16 + launches, &counters));
-    STCHK(ws(ctx, "a_new", n, &a_new));
-    STCHK(ws(ctx, "own_new", n, &own_new));
-    STCHK(ws(ctx, "qobj", qcap, &qobj));
-    STCHK(ws(ctx, "qcand", qcap * kCandCap, &qcand));
-    STCHK(ws(ctx, "qcnt", qcap, &qcnt));
-    STCHK(ws(ctx, "fobj", std::max<int64_t>(n, 1), &fobj));
-    STCHK(ws(ctx, "changed", k, &changed));
-    STCHK(ws(ctx, "obj_partial", nfin + 1, &obj_partial));
-    STCHK(ws(ctx, "objective", 2, &obj));
-    const int nobj = ctx->n_cu * 16;   // workgroups of the exact objective (fixed: a fixed summation order)
-    double* obj64_partial = nullptr;
-    if (ctx->opt.exact_objective) STCHK(ws(ctx, "obj64_partial", nobj, &obj64_partial));
+    if (iter >= 2) STCHK(check_assign(ctx, assign_inout, n, k, "assign_inout (a^[r-1])", w));
+    AssignBufs B;
+    STCHK(assign_buffers(ctx, w, n, k, f->T, &B));
+    const int64_t qcap = B.qcap;
+    unsigned long long* counters = B.counters;
+    int32_t *a_new = B.a_new, *qobj = B.qobj, *qcand = B.qcand, *qcnt = B.qcnt, *fobj = B.fobj;
+    float* own_new = B.own_new;
+    uint8_t* changed = B.changed;
+    double *obj_partial = B.obj_partial, *obj = B.obj;
+    const int nfin = B.nfin, tpl = B.tpl, launches = B.launches, nobj = B.nobj;
+    double* obj64_partial = B.obj64_partial;
 
     WalkArgs A{};
     A.n = n;
@@ -510,30 +617,18 @@ sivf_status assign_impl(sivf_ctx* ctx, const Csr& Xc, const sivf_ivf* f, int32_t
     A.fobj = fobj;
     A.counters = counters;
     A.qcap = qcap;
-    A.st_theta = A.st_best = nullptr;
-    A.st_bj = A.st_cnt = A.st_cj = nullptr;
-    A.st_cr = nullptr;
-    if (launches > 1) {
-        const int64_t m = std::max<int64_t>(n, 1);
-        STCHK(ws(ctx, "st_theta", m, &A.st_theta));
-        STCHK(ws(ctx, "st_best", m, &A.st_best));
-        STCHK(ws(ctx, "st_bj", m, &A.st_bj));
-        STCHK(ws(ctx, "st_cnt", m, &A.st_cnt));
-        STCHK(ws(ctx, "st_cj", m * kCandCap, &A.st_cj));
-        STCHK(ws(ctx, "st_cr", m * kCandCap, &A.st_cr));
-    }
+    A.st_theta = B.st_theta;
+    A.st_best = B.st_best;
+    A.st_bj = B.st_bj;
+    A.st_cnt = B.st_cnt;
+    A.st_cj = B.st_cj;
+    A.st_cr = B.st_cr;
     A.st = f->cur;
     A.relaxed = relaxed;
     A.own64_prev = own64_inout;
-    A.own64_cur = nullptr;
-    A.st_rel = nullptr;
-    int32_t* own64_queue = nullptr;
-    if (relaxed) {
-        const int64_t m = std::max<int64_t>(n, 1);
-        STCHK(ws(ctx, "own64_cur", m, &A.own64_cur));
-        STCHK(ws(ctx, "own64_queue", m, &own64_queue));
-        if (launches > 1) STCHK(ws(ctx, "st_rel", m, &A.st_rel));
-    }
+    A.own64_cur = B.own64_cur;
+    A.st_rel = B.st_rel;
+    int32_t* own64_queue = B.own64_queue;
     A.head = f->H > 0 ? f->head : nullptr;
     A.hval = f->hval;
     A.kpad = (int64_t)f->T * head_ktp(f->kt);
@@ -684,6 +779,11 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->n_cu = ncu;
+    if (scratch_setup(device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return SIVF_E_HIP;
+    }
     for (auto& e : ctx->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
             delete ctx;
@@ -784,7 +884,38 @@ sivf_status sivf_assign(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int
     if (iter < 1) return fail(ctx, SIVF_E_INVALID, "iter must be >= 1");
     Csr Xc;
     STCHK(validate(ctx, X, &Xc));
-    return assign_impl(ctx, Xc, f, iter, assign_inout, own_sim_inout, own64_inout, lambda_out, stats_host);
+    Work w{ctx};
+    return assign_impl(ctx, w, Xc, f, iter, assign_inout, own_sim_inout, own64_inout, lambda_out, stats_host);
+}
+
+sivf_status sivf_assign_noalloc(sivf_ctx* ctx, const sivf_csr* X, const sivf_ivf* f, int32_t iter,
+                                int32_t* assign_inout, float* own_sim_inout, double* own64_inout,
+                                uint8_t* lambda_out, sivf_iter_stats* stats_host) {
+    if (!ctx) return SIVF_E_INVALID;
+    DevGuard g(ctx->device);
+    if (!f || !assign_inout || !own_sim_inout || !lambda_out) return fail(ctx, SIVF_E_INVALID, "NULL argument");
+    if (ctx->opt.filter_mode == SIVF_MODE_RELAXED && !own64_inout)
+        return fail(ctx, SIVF_E_INVALID, "the RELAXED filter needs own64_inout");
+    if (iter < 1) return fail(ctx, SIVF_E_INVALID, "iter must be >= 1");
+    STCHK(check_csr_args(ctx, X, "X"));
+    // the same requests as the run below, counted without memory
+    Work m{ctx, Work::kMeasure};
+    unsigned long long* flags = nullptr;
+    STCHK(m.get("vflags", 4, &flags));
+    if (iter >= 2) STCHK(m.get("aflags", 2, &flags));
+    AssignBufs B;
+    STCHK(assign_buffers(ctx, m, X->n_rows, f->k, f->T, &B));
+    if (m.used > kScratchBytes)
+        return fail(ctx, SIVF_E_UNSUPPORTED,
+                    "sivf_assign_noalloc: %lld objects against %d centroids (%d launches) need %zu bytes of "
+                    "scratch, above its %zu; use sivf_assign", (long long)X->n_rows, f->k, B.launches, m.used,
+                    kScratchBytes);
+    void* base = scratch_of(ctx->device);
+    if (!base) return fail(ctx, SIVF_E_HIP, "no scratch address for device %d", ctx->device);
+    Work w{ctx, Work::kFixed, (char*)base, kScratchBytes};
+    Csr Xc;
+    STCHK(validate(ctx, X, &Xc, w));
+    return assign_impl(ctx, w, Xc, f, iter, assign_inout, own_sim_inout, own64_inout, lambda_out, stats_host);
 }
 
 sivf_status sivf_update(sivf_ctx* ctx, const sivf_csr* X, const int32_t* assign, const uint8_t* lambda,
@@ -822,7 +953,8 @@ sivf_status sivf_run_lloyd(sivf_ctx* ctx, const sivf_csr* X, int32_t k, const in
     int32_t done = 0;
     for (int32_t r = 1; st == SIVF_OK && r <= max_iter; ++r) {
         sivf_iter_stats stt{};
-        st = assign_impl(ctx, Xc, f, r, a, own, own64, lam, &stt);
+        Work w{ctx};
+        st = assign_impl(ctx, w, Xc, f, r, a, own, own64, lam, &stt);
         if (st != SIVF_OK) break;
         done = r;
         if (per_iter_host) per_iter_host[r - 1] = stt;
