@@ -171,101 +171,136 @@ __device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Bat
     sim[c[3]] = o3 + pr[3];
 }
 
-// Dense head rows: 512 consecutive centroids of one row per batch, lane l
-// holding centroids 4l .. 4l+3 and 256 + 4l .. 256 + 4l+3 (two 16-byte loads
-// for binary32; one 16-byte load for bf16, whose rows store each lane's eight
-// values side by side), so each lane's LDS update is two aligned 16-byte
-// read-add-writes, conflict-free across the wave.
+// Dense head rows, accumulated in registers.  The head terms of a chunk are
+// taken one row at a time over a 512-centroid group of the tile: lane l holds
+// the sums of centroids 4l .. 4l + 3 and 256 + 4l .. 256 + 4l + 3 of the
+// group, adds v * row for each head term (one fused multiply-add per
+// centroid), and the group's sums enter the LDS tile once per chunk (one
+// 16-byte read-add-write per lane and 256 centroids).  FP32 rows hold a
+// tile's centroids in order (two 16-byte loads per lane, term and group);
+// BF16 rows interleave each 512-centroid block so that one 16-byte load gives
+// a lane both of its 4-centroid groups.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-struct DBatch {
-    u32x4 a, b;
-};
-
-// One head row's slots of one tile (ktp values of the posting dtype) as a
-// buffer of its own: offsets inside it stay below 16 KiB, so the rows
-// together may span any number of bytes.
-template <bool BF16>
-__device__ inline __amdgpu_buffer_rsrc_t head_rsrc(const WalkArgs& A, int32_t row, int tile, int ktp) {
-    const int64_t esz = BF16 ? 2 : 4;
-    const char* base = (const char*)A.hval + ((int64_t)row * A.kpad + (int64_t)tile * ktp) * esz;
-    return span_rsrc(base, (int64_t)ktp * esz);
-}
+constexpr int kHeadGroup = 512;   // centroids of one register-held group
 
 // bytes one wave's vector loads request (64 lanes x width), for the walk's
-// load counter: a list batch (ids + values), a head-row batch, a record
+// load counter: a list batch (ids + values), a record
 constexpr uint32_t kListBatchBytes32 = 2 * 256 + 2 * 512;
 constexpr uint32_t kListBatchBytes16 = 2 * 256 + 2 * 256;
-constexpr uint32_t kHeadBatchBytes32 = 2 * 1024;
-constexpr uint32_t kHeadLoadBytes16 = 1024;
 constexpr uint32_t kRecordBytes = 64 * 16;
 
-// FP32 rows: one 512-centroid batch is two 16-byte loads per lane, centroids
-// 4l..4l+3 and 256+4l..256+4l+3 of the batch; ub is the batch's first slot
-// in the tile
-__device__ inline DBatch dense_load32(__amdgpu_buffer_rsrc_t dd, int ub, int lane) {
-    DBatch r;
-    r.a = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, ub * 4, 0);
-    r.b = __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16 + 1024, ub * 4, 0);
-    return r;
+struct HAcc {
+    float4 a, b;   // centroids 4l.. and 256 + 4l.. of the group
+};
+
+template <bool BF16>
+struct HRow {
+    u32x4 a, b;    // FP32: the two 4-centroid groups; BF16: a holds both (b unused)
+};
+
+// One head row's slots of one tile from slot `at` on, as a buffer of its own
+// holding `slots` values: offsets stay below 2 KiB, so the rows together may
+// span any number of bytes, and loads past `slots` read 0 without touching
+// memory.
+template <bool BF16>
+__device__ inline __amdgpu_buffer_rsrc_t head_rsrc(const WalkArgs& A, int32_t row, int tile, int ktp, int at,
+                                                   int slots) {
+    const int64_t esz = BF16 ? 2 : 4;
+    const char* base = (const char*)A.hval + ((int64_t)row * A.kpad + (int64_t)tile * ktp + at) * esz;
+    return span_rsrc(base, (int64_t)slots * esz);
 }
 
-// BF16 rows are stored interleaved per 512-centroid batch: one 16-byte load
-// per lane gives the same two 4-centroid groups (.x .y, then .z .w)
-__device__ inline u32x4 dense_load16(__amdgpu_buffer_rsrc_t dd, int ub, int lane) {
-    return __builtin_amdgcn_raw_buffer_load_b128(dd, lane * 16, ub * 2, 0);
+template <bool BF16>
+__device__ inline HRow<BF16> hrow_load(__amdgpu_buffer_rsrc_t r, int lane) {
+    HRow<BF16> h;
+    h.a = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16, 0, 0);
+    if (!BF16) h.b = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + 1024, 0, 0);
+    return h;
 }
 
-__device__ inline void dense_unit32(float* sim, u32x4 w, int c0, float xv) {
-    float4* q = (float4*)(sim + c0);
-    float4 o = *q;
-    o.x = o.x + xv * __uint_as_float(w.x);
-    o.y = o.y + xv * __uint_as_float(w.y);
-    o.z = o.z + xv * __uint_as_float(w.z);
-    o.w = o.w + xv * __uint_as_float(w.w);
-    *q = o;
+__device__ inline float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+__device__ inline void fma4(float4& s, float x, float a, float b, float c, float d) {
+    s.x = __builtin_fmaf(x, a, s.x);
+    s.y = __builtin_fmaf(x, b, s.y);
+    s.z = __builtin_fmaf(x, c, s.z);
+    s.w = __builtin_fmaf(x, d, s.w);
 }
 
-// sim[ub + c] += xv * row[ub + c] for the batch's centroids below kt
-__device__ inline void dense_accumulate32(float* sim, const DBatch& b, int ub, int kt, float xv, int lane) {
-    const int c0 = ub + 4 * lane, c1 = ub + 256 + 4 * lane;
-    if (ub + 512 <= kt) {
-        dense_unit32(sim, b.a, c0, xv);
-        dense_unit32(sim, b.b, c1, xv);
+template <bool BF16>
+__device__ inline void hrow_fma(HAcc& acc, const HRow<BF16>& h, float x) {
+    if (BF16) {
+        fma4(acc.a, x, bf_lo(h.a.x), bf_hi(h.a.x), bf_lo(h.a.y), bf_hi(h.a.y));
+        fma4(acc.b, x, bf_lo(h.a.z), bf_hi(h.a.z), bf_lo(h.a.w), bf_hi(h.a.w));
     } else {
-        // tile width not a multiple of 512: the lanes past it hold no centroid
-        if (c0 < kt) dense_unit32(sim, b.a, c0, xv);
-        if (c1 < kt) dense_unit32(sim, b.b, c1, xv);
+        fma4(acc.a, x, __uint_as_float(h.a.x), __uint_as_float(h.a.y), __uint_as_float(h.a.z),
+             __uint_as_float(h.a.w));
+        fma4(acc.b, x, __uint_as_float(h.b.x), __uint_as_float(h.b.y), __uint_as_float(h.b.z),
+             __uint_as_float(h.b.w));
     }
 }
 
-// two head terms in one read-add-write of four similarities: the additions
-// keep the order of two separate passes (first term, then second)
-__device__ inline void dense_unit16x2(float* sim, uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1, int c0,
-                                      float xa, float xb) {
-    float4* q = (float4*)(sim + c0);
+__device__ inline void add4(float* p, const float4& v) {
+    float4* q = (float4*)p;
     float4 o = *q;
-    o.x = o.x + xa * __uint_as_float(a0 << 16);
-    o.y = o.y + xa * __uint_as_float(a0 & 0xffff0000u);
-    o.z = o.z + xa * __uint_as_float(a1 << 16);
-    o.w = o.w + xa * __uint_as_float(a1 & 0xffff0000u);
-    o.x = o.x + xb * __uint_as_float(b0 << 16);
-    o.y = o.y + xb * __uint_as_float(b0 & 0xffff0000u);
-    o.z = o.z + xb * __uint_as_float(b1 << 16);
-    o.w = o.w + xb * __uint_as_float(b1 & 0xffff0000u);
+    o.x = o.x + v.x;
+    o.y = o.y + v.y;
+    o.z = o.z + v.z;
+    o.w = o.w + v.w;
     *q = o;
 }
 
-__device__ inline void dense_accumulate16x2(float* sim, u32x4 wa, u32x4 wb, int ub, int kt, float xa, float xb,
-                                            int lane) {
-    const int c0 = ub + 4 * lane, c1 = ub + 256 + 4 * lane;
-    if (ub + 512 <= kt) {
-        dense_unit16x2(sim, wa.x, wa.y, wb.x, wb.y, c0, xa, xb);
-        dense_unit16x2(sim, wa.z, wa.w, wb.z, wb.w, c1, xa, xb);
-    } else {
-        if (c0 < kt) dense_unit16x2(sim, wa.x, wa.y, wb.x, wb.y, c0, xa, xb);
-        if (c1 < kt) dense_unit16x2(sim, wa.z, wa.w, wb.z, wb.w, c1, xa, xb);
+// The head terms of one chunk (bits of dl: lanes whose term has a head row
+// hrow, with object value v) over the tile's slots [0, dl_lim): per group of
+// 512 centroids, every term's row is loaded (the next term's loads in flight
+// while the current one is added) and summed in registers, then the sums are
+// merged into the tile below kt.  Returns the 4-byte words the loads fetch.
+template <bool BF16>
+__device__ inline uint32_t head_terms(const WalkArgs& A, float* sim, unsigned long long dl, int32_t hrow, float v,
+                                      int tile, int ktp, int dl_lim, int lane) {
+    const uint32_t nt = (uint32_t)__popcll(dl);
+    uint32_t words = 0;
+    for (int at = 0; at < dl_lim; at += kHeadGroup) {
+        const int rem = min(dl_lim - at, kHeadGroup);
+        // slots the loads may read: whole 256-centroid groups (FP32) or the
+        // 512-centroid interleaved block (BF16)
+        const int lim = BF16 ? kHeadGroup : (rem + 255) & ~255;
+        words += nt * (uint32_t)lim * (BF16 ? 2u : 4u) / 4u;
+        HAcc acc;
+        acc.a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        acc.b = acc.a;
+        unsigned long long m = dl;
+        int q = __builtin_ctzll(m);
+        m &= m - 1;
+        float x0 = bcast_f32(v, q), x1 = 0.0f;
+        HRow<BF16> X = hrow_load<BF16>(head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp, at, lim), lane), Y;
+        for (;;) {
+            if (!m) {
+                hrow_fma<BF16>(acc, X, x0);
+                break;
+            }
+            q = __builtin_ctzll(m);
+            m &= m - 1;
+            x1 = bcast_f32(v, q);
+            Y = hrow_load<BF16>(head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp, at, lim), lane);
+            hrow_fma<BF16>(acc, X, x0);
+            if (!m) {
+                hrow_fma<BF16>(acc, Y, x1);
+                break;
+            }
+            q = __builtin_ctzll(m);
+            m &= m - 1;
+            x0 = bcast_f32(v, q);
+            X = hrow_load<BF16>(head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp, at, lim), lane);
+            hrow_fma<BF16>(acc, Y, x1);
+        }
+        const int c0 = at + 4 * lane, c1 = c0 + 256;
+        if (c0 < A.kt) add4(sim + c0, acc.a);
+        if (256 < lim && c1 < A.kt) add4(sim + c1, acc.b);
     }
+    return words;
 }
 
 // ---------------------------------------------------------------------------
@@ -317,7 +352,7 @@ __device__ double exact_rho(const WalkArgs& A, const Store& st, int64_t r0, int 
 // at N=8M, k=10k; the FP32 ones stay at the compiler's choice (5 waves),
 // where the cap's spills cost more than the extra wave gains.
 template <bool BF16, bool CB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 1))) void k_walk_fast(WalkArgs A, unsigned long long* __restrict__ work, int tb,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 5))) void k_walk_fast(WalkArgs A, unsigned long long* __restrict__ work, int tb,
                                                    int te) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -331,7 +366,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     for (int jj = lane; jj < A.kt; jj += 64) sim[jj] = 0.0f;
 
     unsigned long long macc = 0, icp_cnt = 0, rel_cnt = 0;
-    uint64_t lbytes = 0;   // bytes requested by this wave's vector loads
+    uint32_t lwords = 0;   // 4-byte words requested by this wave's vector loads (flushed at 2^31)
     const uint32_t xb = 4u + (A.x_f64 ? 8u : 4u);   // one staged term: column + value
     constexpr int kGrab = 8;
     for (int64_t g0 = wave_grab(work, kGrab); g0 < A.n; g0 = wave_grab(work, kGrab)) {
@@ -416,7 +451,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 tt[h] = t;
                 tv[h] = load_xval(A.xval, A.x_f64, r0 + h);
             }
-            lbytes += (uint64_t)min(n, kTermCap) * xb;
+            lwords += (uint32_t)min(n, kTermCap) * (xb / 4);
+            if (lwords >= 0x80000000u) {   // wave-uniform; far below any one object's share
+                if (lane == 0) atomicAdd(&A.counters[10], 4ull * lwords);
+                lwords = 0;
+            }
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
             const int nch = max(1, (n + 63) >> 6);
@@ -446,7 +485,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 }
                 nrec = A.rec[(int64_t)tl * A.d + (nin ? t : 0)];
                 nv = nin ? xv : 0.0f;
-                lbytes += kRecordBytes + (hb < kTermCap ? 0u : 64u * xb);
+                lwords += (kRecordBytes + (hb < kTermCap ? 0u : 64u * xb)) / 4;
             };
             seg_load(0);
             for (int pi = 0; pi < npairs; ++pi) {
@@ -478,114 +517,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 // constant, the batch offset is scalar, and lanes past the
                 // list's end read 0 from the hardware range check.
                 // ---- head terms: dense rows (in the ICP branch their moving
-                // prefix only), in ascending term order, 512 centroids per
-                // batch, next batch in flight while the current one is
-                // accumulated
+                // prefix only), in ascending term order, whole rows of a
+                // 1024-centroid group summed in registers, one merge into
+                // the tile per chunk
                 int hrow = -1;
                 const bool use_head = A.head && !(filt && CB);
                 if (use_head && h < n) hrow = hr;
-                unsigned long long dl = ballot(hrow >= 0);
-                if (dl && BF16) {
-                    // two terms per pass over the tile (a lone last term is paired
-                    // with its own row at weight 0, which adds +-0 exactly)
-                    float pa = 0.0f, pb = 0.0f;
-                    __amdgpu_buffer_rsrc_t da, db;
-                    auto take = [&]() -> bool {
-                        if (!dl) return false;
-                        int q = __builtin_ctzll(dl);
-                        dl &= dl - 1;
-                        pa = bcast_f32(v, q);
-                        const int32_t row_a = bcast_i32(hrow, q);
-                        int32_t row_b = row_a;
-                        pb = 0.0f;
-                        if (dl) {
-                            q = __builtin_ctzll(dl);
-                            dl &= dl - 1;
-                            pb = bcast_f32(v, q);
-                            row_b = bcast_i32(hrow, q);
-                        }
-                        da = head_rsrc<BF16>(A, row_a, tile, ktp);
-                        db = head_rsrc<BF16>(A, row_b, tile, ktp);
-                        return true;
-                    };
-                    take();
-                    int ub = 0;
-                    auto padv = [&]() -> bool {
-                        ub += 512;
-                        if (ub < dlim) return true;
-                        ub = 0;
-                        return take();
-                    };
-                    u32x4 Xa = dense_load16(da, ub, lane), Xb = dense_load16(db, ub, lane), Ya, Yb;
-                    lbytes += 2 * kHeadLoadBytes16;
-                    int xu = ub, yu = 0;
-                    float xa = pa, xb = pb, ya = 0.0f, yb = 0.0f;
-                    for (;;) {
-                        if (!padv()) {
-                            dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
-                            break;
-                        }
-                        Ya = dense_load16(da, ub, lane);
-                        Yb = dense_load16(db, ub, lane);
-                        lbytes += 2 * kHeadLoadBytes16;
-                        yu = ub;
-                        ya = pa;
-                        yb = pb;
-                        dense_accumulate16x2(sim, Xa, Xb, xu, A.kt, xa, xb, lane);
-                        if (!padv()) {
-                            dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
-                            break;
-                        }
-                        Xa = dense_load16(da, ub, lane);
-                        Xb = dense_load16(db, ub, lane);
-                        lbytes += 2 * kHeadLoadBytes16;
-                        xu = ub;
-                        xa = pa;
-                        xb = pb;
-                        dense_accumulate16x2(sim, Ya, Yb, yu, A.kt, ya, yb, lane);
-                    }
-                } else if (dl) {
-                    int q = __builtin_ctzll(dl);
-                    dl &= dl - 1;
-                    int ub = 0;
-                    float xv = bcast_f32(v, q);
-                    __amdgpu_buffer_rsrc_t dr = head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp);
-                    auto dadv = [&]() -> bool {
-                        ub += 512;
-                        if (ub < dlim) return true;
-                        if (!dl) return false;
-                        q = __builtin_ctzll(dl);
-                        dl &= dl - 1;
-                        ub = 0;
-                        xv = bcast_f32(v, q);
-                        dr = head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp);
-                        return true;
-                    };
-                    DBatch X = dense_load32(dr, ub, lane), Y;
-                    lbytes += kHeadBatchBytes32;
-                    int xu = ub, yu = 0;
-                    float xx = xv, yx = 0.0f;
-                    for (;;) {
-                        if (!dadv()) {
-                            dense_accumulate32(sim, X, xu, A.kt, xx, lane);
-                            break;
-                        }
-                        Y = dense_load32(dr, ub, lane);
-                        lbytes += kHeadBatchBytes32;
-                        yu = ub;
-                        yx = xv;
-                        dense_accumulate32(sim, X, xu, A.kt, xx, lane);
-                        if (!dadv()) {
-                            dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
-                            break;
-                        }
-                        X = dense_load32(dr, ub, lane);
-                        lbytes += kHeadBatchBytes32;
-                        xu = ub;
-                        xx = xv;
-                        dense_accumulate32(sim, Y, yu, A.kt, yx, lane);
-                    }
-                }
+                const unsigned long long dl = ballot(hrow >= 0);
+                if (dl) lwords += head_terms<BF16>(A, sim, dl, hrow, v, tile, ktp, dlim, lane);
                 // ---- other terms: structured lists
                 unsigned long long live = ballot(h < n && e > s0 && hrow < 0);
                 if (live) {
@@ -602,6 +541,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         const int64_t b0 = ls & ~(int64_t)7;
                         lo = (int)(ls - b0);
                         hi = (int)(bcast_i64(e, q) - b0);
+                        lwords += (uint32_t)((hi + kBatch - 1) / kBatch) * ((BF16 ? kListBatchBytes16 : kListBatchBytes32) / 4);
                         lv = bcast_f32(v, q);
                         off = 0;
                         // extent rounded up to whole groups of 8 (the arrays keep
@@ -613,9 +553,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         return true;
                     };
                     next_list();
-                    constexpr uint32_t lbb = BF16 ? kListBatchBytes16 : kListBatchBytes32;
                     Batch X = load_batch<BF16>(dc, dv, off, lane), Y;
-                    lbytes += lbb;
                     int xs = lo - off, xe = hi - off, ys = 0, ye = 0;
                     float xv = lv, yv = 0.0f;
                     off += kBatch;
@@ -625,8 +563,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             break;
                         }
                         Y = load_batch<BF16>(dc, dv, off, lane);
-                        lbytes += lbb;
-                        ys = lo - off;
+                            ys = lo - off;
                         ye = hi - off;
                         yv = lv;
                         off += kBatch;
@@ -636,8 +573,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                             break;
                         }
                         X = load_batch<BF16>(dc, dv, off, lane);
-                        lbytes += lbb;
-                        xs = lo - off;
+                            xs = lo - off;
                         xe = hi - off;
                         xv = lv;
                         off += kBatch;
@@ -794,7 +730,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     macc = (unsigned long long)wave_sum_i64((int64_t)macc);
     if (lane == 0) {
         atomicAdd(&A.counters[0], macc);
-        atomicAdd(&A.counters[10], (unsigned long long)lbytes);
+        atomicAdd(&A.counters[10], 4ull * lwords);
         atomicAdd(&A.counters[3], icp_cnt);
         if (rel_cnt) atomicAdd(&A.counters[7], rel_cnt);
     }

@@ -69,8 +69,8 @@ __global__ __launch_bounds__(256) void k_probe_load(const uint8_t* __restrict__ 
 
 // LDS: every lane reads (or writes) 16 bytes per operation from a 32 KiB
 // workgroup buffer, 8 operations per round, consecutive lanes on consecutive
-// 16-byte entries (conflict free); the entries move with the round so no
-// access repeats the previous round's.
+// 16-byte entries (conflict free); the entries rotate by one group of 256
+// per round, so a round's addresses differ from the previous round's.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_probe_lds(int rounds, uint32_t never, uint32_t* __restrict__ sink,
                                                    unsigned long long* __restrict__ clk) {
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_probe_lds(int rounds, uint32_t never, u
     for (int it = 0; it < rounds; ++it) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int idx = (threadIdx.x + (u + it * 8) * 256) & 2047;
+            const int idx = (threadIdx.x + (u + it) * 256) & 2047;
             if (WRITE) {
                 lds[idx] = acc;
                 acc.x += 1u;
