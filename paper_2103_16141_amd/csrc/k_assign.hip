@@ -199,23 +199,21 @@ struct HRow {
     u32x4 a, b;    // FP32: the two 4-centroid groups; BF16: a holds both (b unused)
 };
 
-// One head row's slots of one tile from slot `at` on, as a buffer of its own
-// holding `slots` values: offsets stay below 2 KiB, so the rows together may
-// span any number of bytes, and loads past `slots` read 0 without touching
-// memory.
-template <bool BF16>
-__device__ inline __amdgpu_buffer_rsrc_t head_rsrc(const WalkArgs& A, int32_t row, int tile, int ktp, int at,
-                                                   int slots) {
-    const int64_t esz = BF16 ? 2 : 4;
-    const char* base = (const char*)A.hval + ((int64_t)row * A.kpad + (int64_t)tile * ktp + at) * esz;
-    return span_rsrc(base, (int64_t)slots * esz);
+// A head row's slots of a tile as a buffer: base = the byte address of the
+// tile's first slot in the row (kept per term as two 32-bit halves), `bytes`
+// the extent; loads past it read 0 without touching memory.  Offsets stay
+// below 16 KiB, so the rows together may span any number of bytes.
+__device__ inline __amdgpu_buffer_rsrc_t head_rsrc(uint32_t lo, uint32_t hi, int bytes) {
+    const uint64_t base = ((uint64_t)hi << 32) | lo;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, 0x00020000);
 }
 
+// vo: the lane's byte offset (16 * lane plus the group's start)
 template <bool BF16>
-__device__ inline HRow<BF16> hrow_load(__amdgpu_buffer_rsrc_t r, int lane) {
+__device__ inline HRow<BF16> hrow_load(__amdgpu_buffer_rsrc_t r, int vo) {
     HRow<BF16> h;
-    h.a = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16, 0, 0);
-    if (!BF16) h.b = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + 1024, 0, 0);
+    h.a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 0, 0);
+    if (!BF16) h.b = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 1024, 0, 0);
     return h;
 }
 
@@ -253,48 +251,64 @@ __device__ inline void add4(float* p, const float4& v) {
 }
 
 // The head terms of one chunk (bits of dl: lanes whose term has a head row
-// hrow, with object value v) over the tile's slots [0, dl_lim): per group of
-// 512 centroids, every term's row is loaded (the next term's loads in flight
-// while the current one is added) and summed in registers, then the sums are
-// merged into the tile below kt.  Returns the 4-byte words the loads fetch.
+// hrow, with object value v) over the tile's slots [0, dl_lim).  First each
+// such lane computes the byte address of its row's slice for this tile, and a
+// lane permutation moves the i-th head term (ascending term order) to lane i,
+// so the loop below walks terms by a counter and takes each term's address
+// and value with lane reads, with no per-term address arithmetic.  Then per
+// group of 512 centroids, every term's row is loaded (the next term's loads in
+// flight while the current one is added) and summed in registers, and the
+// sums are merged into the tile below kt.  Returns the 4-byte words fetched.
 template <bool BF16>
 __device__ inline uint32_t head_terms(const WalkArgs& A, float* sim, unsigned long long dl, int32_t hrow, float v,
                                       int tile, int ktp, int dl_lim, int lane) {
-    const uint32_t nt = (uint32_t)__popcll(dl);
+    const int nt = __popcll(dl);
+    const bool mine = (dl >> lane) & 1ull;
+    const uint64_t esz = BF16 ? 2 : 4;
+    const uint64_t addr = (uint64_t)A.hval +
+                          ((uint64_t)(uint32_t)(mine ? hrow : 0) * (uint64_t)A.kpad + (uint64_t)tile * ktp) * esz;
+    // destination lane: rank among the head lanes, the others after them
+    const int rank = mine ? lanes_below(dl) : nt + lanes_below(~dl);
+    const uint32_t plo = (uint32_t)__builtin_amdgcn_ds_permute(rank * 4, (int)(uint32_t)addr);
+    const uint32_t phi = (uint32_t)__builtin_amdgcn_ds_permute(rank * 4, (int)(uint32_t)(addr >> 32));
+    const float pv = __int_as_float(__builtin_amdgcn_ds_permute(rank * 4, __float_as_int(v)));
     uint32_t words = 0;
     for (int at = 0; at < dl_lim; at += kHeadGroup) {
         const int rem = min(dl_lim - at, kHeadGroup);
         // slots the loads may read: whole 256-centroid groups (FP32) or the
         // 512-centroid interleaved block (BF16)
         const int lim = BF16 ? kHeadGroup : (rem + 255) & ~255;
-        words += nt * (uint32_t)lim * (BF16 ? 2u : 4u) / 4u;
+        const int bytes = lim * (int)esz;
+        const int end = (at + lim) * (int)esz;   // extent of the buffer from the tile's first slot
+        const int vo = 16 * lane + at * (int)esz;
+        words += (uint32_t)nt * (uint32_t)bytes / 4u;
         HAcc acc;
         acc.a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         acc.b = acc.a;
-        unsigned long long m = dl;
-        int q = __builtin_ctzll(m);
-        m &= m - 1;
-        float x0 = bcast_f32(v, q), x1 = 0.0f;
-        HRow<BF16> X = hrow_load<BF16>(head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp, at, lim), lane), Y;
-        for (;;) {
-            if (!m) {
-                hrow_fma<BF16>(acc, X, x0);
-                break;
-            }
-            q = __builtin_ctzll(m);
-            m &= m - 1;
-            x1 = bcast_f32(v, q);
-            Y = hrow_load<BF16>(head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp, at, lim), lane);
-            hrow_fma<BF16>(acc, X, x0);
-            if (!m) {
-                hrow_fma<BF16>(acc, Y, x1);
-                break;
-            }
-            q = __builtin_ctzll(m);
-            m &= m - 1;
-            x0 = bcast_f32(v, q);
-            X = hrow_load<BF16>(head_rsrc<BF16>(A, bcast_i32(hrow, q), tile, ktp, at, lim), lane);
-            hrow_fma<BF16>(acc, Y, x1);
+        auto term = [&](int i, float& x) -> HRow<BF16> {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)plo, i);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)phi, i);
+            x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv), i));
+            return hrow_load<BF16>(head_rsrc(lo, hi, end), vo);
+        };
+        // two terms per trip, one loop exit, so the sums stay in the same
+        // registers (no copies between the two halves)
+        float xa, xb;
+        HRow<BF16> RA = term(0, xa), RB;
+        int i = 1;
+        while (i + 1 < nt) {
+            RB = term(i, xb);
+            hrow_fma<BF16>(acc, RA, xa);
+            RA = term(i + 1, xa);
+            hrow_fma<BF16>(acc, RB, xb);
+            i += 2;
+        }
+        if (i < nt) {
+            RB = term(i, xb);
+            hrow_fma<BF16>(acc, RA, xa);
+            hrow_fma<BF16>(acc, RB, xb);
+        } else {
+            hrow_fma<BF16>(acc, RA, xa);
         }
         const int c0 = at + 4 * lane, c1 = c0 + 256;
         if (c0 < A.kt) add4(sim + c0, acc.a);
