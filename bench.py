@@ -252,10 +252,11 @@ def summarize(stats, wall, sizes, nnz, n, posting):
     t_update = sum(s["t_update_ms"] for s in stats) / 1e3
     bytes_ = sum(algorithmic_bytes(s, nnz, n, sizes["n_tiles"], posting) for s in stats)
     loaded = sum(s["walk_bytes"] for s in stats)
+    wide = sum(s["walk_wide_bytes"] for s in stats)
     return dict(multadds=M, multadds_per_s=M / t_assign, s_per_iter=wall / len(stats),
                 assign_s=t_assign, walk_s=t_walk, update_s=t_update,
                 walk_multadds_per_s=M / t_walk, walk_algorithmic_gbs=bytes_ / t_walk / 1e9,
-                walk_loaded_bytes=loaded, walk_data_gbs=loaded / t_walk / 1e9,
+                walk_loaded_bytes=loaded, walk_wide_bytes=wide, walk_data_gbs=loaded / t_walk / 1e9,
                 walk_launches=sum(s["walk_launches"] for s in stats),
                 iter1_multadds_per_s=stats[0]["multadds"] / (stats[0]["t_assign_ms"] / 1e3),
                 rescored_objects=sum(s["rescored_objects"] for s in stats),
@@ -385,12 +386,20 @@ def main():
     # the walk is one kernel launch per group of tiles_per_launch centroid tiles
     launches = s32["walk_launches"]
     launch_ms = s32["walk_s"] * 1e3 / launches
-    # Roofline of the walk: the vector memory data path, whose load rate per CU
-    # (measured by the probe on L1-resident 16-byte loads) times 256 CUs at the
-    # 2.4 GHz peak clock is the peak; achieved = bytes the walk's vector loads
-    # request (counted by the kernel) over its launch time.
+    # Roofline of the walk: the vector memory data path.  Its peak is what the
+    # walk's own mix of loads could move per launch at the probed per-CU rates
+    # (16-byte loads at the L1-resident b128 rate, 4- and 8-byte loads at the
+    # b64 rate), over 256 CUs at the 2.4 GHz peak clock; achieved = the bytes
+    # the walk's vector loads request (counted by the kernel) over its launch
+    # time.
     achieved = s32["walk_data_gbs"]
-    peak = probe["l1_b128"]["bytes_per_clk_cu"] * N_CU * CLOCK_GHZ if probe else None
+    peak = peak16 = None
+    if probe:
+        r16 = probe["l1_b128"]["bytes_per_clk_cu"] * N_CU * CLOCK_GHZ
+        r8 = probe["l1_b64"]["bytes_per_clk_cu"] * N_CU * CLOCK_GHZ
+        wide, narrow = s32["walk_wide_bytes"], s32["walk_loaded_bytes"] - s32["walk_wide_bytes"]
+        peak = (wide + narrow) / (wide / r16 + narrow / r8)
+        peak16 = r16
     traffic = measured_traffic()
     dram = None
     if traffic:
@@ -403,7 +412,10 @@ def main():
                 "traffic": traffic["dram_bytes_per_launch"] if traffic else None,
                 "kernel": WALK_KERNEL, "launches": launches, "launch_avg_ms": launch_ms,
                 "bytes_per_launch": s32["walk_loaded_bytes"] / launches,
-                "peak_basis": "probe l1_b128 bytes/clk/CU x %d CUs x %.1f GHz" % (N_CU, CLOCK_GHZ),
+                "wide_load_fraction": s32["walk_wide_bytes"] / s32["walk_loaded_bytes"],
+                "peak_basis": "walk's load mix at the probed L1 rates (b128 for 16-byte loads, b64 for 4-/8-byte "
+                              "loads) x %d CUs x %.1f GHz" % (N_CU, CLOCK_GHZ),
+                "peak_all_16byte_loads": peak16,
                 "dram": dram,
                 "algorithmic_gbs": s32["walk_algorithmic_gbs"],
                 "algorithmic_frac_of_hbm_peak": s32["walk_algorithmic_gbs"] / HBM_PEAK_GBS,

@@ -150,6 +150,8 @@ typedef struct {
     int64_t walk_bytes;          /* bytes requested by the fast pass's vector loads
                                     (64 lanes x load width per load issued: posting and
                                     head-row batches, segment records, staged terms) */
+    int64_t walk_wide_bytes;     /* of which 16-byte-per-lane loads (dense head rows and
+                                    segment records; the rest are 4- and 8-byte loads) */
     int32_t walk_launches;       /* fast-pass kernel launches of this step */
     int32_t reserved;
 } sivf_iter_stats;

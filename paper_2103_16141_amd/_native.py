@@ -34,6 +34,7 @@ class sivf_iter_stats(ctypes.Structure):
                 ("objective_fast", ctypes.c_double), ("t_walk_ms", ctypes.c_float),
                 ("t_assign_ms", ctypes.c_float), ("t_update_ms", ctypes.c_float), ("head_rows", ctypes.c_int64),
                 ("relaxed_objects", ctypes.c_int64), ("objective", ctypes.c_double), ("walk_bytes", ctypes.c_int64),
+                ("walk_wide_bytes", ctypes.c_int64),
                 ("walk_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):

@@ -658,7 +658,7 @@ sivf_status assign_impl(sivf_ctx* ctx, Work& w, const Csr& Xc, const sivf_ivf* f
     if (ctx->opt.exact_objective)
         HIPCHK(ctx, objective64(A, f->cur, assign_inout, obj64_partial, nobj, obj + 1, s));
     if (stats_host) {
-        unsigned long long c[11];
+        unsigned long long c[12];
         double o[2] = {0.0, 0.0};
         HIPCHK(ctx, hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipMemcpyAsync(o, obj, sizeof(o), hipMemcpyDeviceToHost, s));
@@ -677,6 +677,7 @@ sivf_status assign_impl(sivf_ctx* ctx, Work& w, const Csr& Xc, const sivf_ivf* f
         stats_host->head_rows = f->H;
         stats_host->relaxed_objects = (int64_t)c[7];
         stats_host->walk_bytes = (int64_t)c[10];
+        stats_host->walk_wide_bytes = (int64_t)c[11];
         stats_host->walk_launches = launches;
         float t = 0.0f;
         HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));

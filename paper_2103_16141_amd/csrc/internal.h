@@ -78,6 +78,7 @@ struct WalkArgs {
                                    // [4] re-scored candidates [5] moved [6] invariant
                                    // [7] relaxed-ICP objects [9] own64 queue length
                                    // [10] bytes requested by the walk's vector loads
+                                   // [11] of which 16-byte-per-lane loads
                                    // [16 + launch] walk work counters
     int64_t qcap;           // capacity of the candidate queue
     // dense head rows (nullptr head: none)

@@ -92,36 +92,39 @@ __device__ inline __amdgpu_buffer_rsrc_t span_rsrc(const void* base, int64_t byt
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// 256 postings of one list in two halves of 128: lane l holds postings 2l
-// and 2l+1 of each half, fetched as whole words (the compiler then never
+// 256 postings of one list: lane l holds postings 4l .. 4l+3, fetched as one
+// 8-byte load of their 16-bit ids and one 16-byte (FP32) or 8-byte (BF16)
+// load of their values, whole words throughout (the compiler then never
 // widens or packs 16-bit values while their loads are in flight).
-//   ca, cb    : two 16-bit ids each (low half = even posting)
-//   ua*, ub*  : binary32 values (fp32), or two bf16 values in ua0 / ub0
+//   c01, c23 : two 16-bit ids each (low half = the lower posting)
+//   u0..u3   : binary32 values (FP32), or two bf16 values in u0 and u1 each
 constexpr int kBatch = 256;
 
 struct Batch {
-    uint32_t ca, cb, ua0, ua1, ub0, ub1;
+    uint32_t c01, c23, u0, u1, u2, u3;
 };
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <bool BF16>
 __device__ inline Batch load_batch(__amdgpu_buffer_rsrc_t dc, __amdgpu_buffer_rsrc_t dv, int off, int lane) {
     Batch b;
-    b.ca = __builtin_amdgcn_raw_buffer_load_b32(dc, lane * 4, off * 2, 0);
-    b.cb = __builtin_amdgcn_raw_buffer_load_b32(dc, lane * 4 + 256, off * 2, 0);
+    const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(dc, lane * 8, off * 2, 0);
+    b.c01 = c.x;
+    b.c23 = c.y;
     if (BF16) {
-        b.ua0 = __builtin_amdgcn_raw_buffer_load_b32(dv, lane * 4, off * 2, 0);
-        b.ub0 = __builtin_amdgcn_raw_buffer_load_b32(dv, lane * 4 + 256, off * 2, 0);
-        b.ua1 = 0;
-        b.ub1 = 0;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(dv, lane * 8, off * 2, 0);
+        b.u0 = v.x;
+        b.u1 = v.y;
+        b.u2 = 0;
+        b.u3 = 0;
     } else {
-        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(dv, lane * 8, off * 4, 0);
-        const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(dv, lane * 8 + 512, off * 4, 0);
-        b.ua0 = a.x;
-        b.ua1 = a.y;
-        b.ub0 = c.x;
-        b.ub1 = c.y;
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(dv, lane * 16, off * 4, 0);
+        b.u0 = v.x;
+        b.u1 = v.y;
+        b.u2 = v.z;
+        b.u3 = v.w;
     }
     return b;
 }
@@ -129,46 +132,43 @@ __device__ inline Batch load_batch(__amdgpu_buffer_rsrc_t dc, __amdgpu_buffer_rs
 // sim[c] += vq * u for the batch's postings whose position relative to the
 // batch start lies in [bs, be).  They belong to one list, so their ids are
 // distinct: all four are read first, then written.  In a partial batch the
-// lanes outside the list use their own spare slot sim[kt + lane] instead
-// (no branches).  CB (IVF-CBICP) zeroes the products of invariant centroids
-// instead of stopping lists early.
+// lane's postings outside the list use its own spare slot sim[kt + lane]
+// instead (no branches).  CB (IVF-CBICP) zeroes the products of invariant
+// centroids instead of stopping lists early.
 template <bool BF16, bool CB>
 __device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Batch& b, int bs, int be, float vq,
                                         int lane, bool test_flag, int32_t base) {
-    uint32_t c[4] = {b.ca & 0xffffu, b.ca >> 16, b.cb & 0xffffu, b.cb >> 16};
+    uint32_t c[4] = {b.c01 & 0xffffu, b.c01 >> 16, b.c23 & 0xffffu, b.c23 >> 16};
     float u[4];
     if (BF16) {
-        u[0] = __uint_as_float(b.ua0 << 16);
-        u[1] = __uint_as_float(b.ua0 & 0xffff0000u);
-        u[2] = __uint_as_float(b.ub0 << 16);
-        u[3] = __uint_as_float(b.ub0 & 0xffff0000u);
+        u[0] = __uint_as_float(b.u0 << 16);
+        u[1] = __uint_as_float(b.u0 & 0xffff0000u);
+        u[2] = __uint_as_float(b.u1 << 16);
+        u[3] = __uint_as_float(b.u1 & 0xffff0000u);
     } else {
-        u[0] = __uint_as_float(b.ua0);
-        u[1] = __uint_as_float(b.ua1);
-        u[2] = __uint_as_float(b.ub0);
-        u[3] = __uint_as_float(b.ub1);
+        u[0] = __uint_as_float(b.u0);
+        u[1] = __uint_as_float(b.u1);
+        u[2] = __uint_as_float(b.u2);
+        u[3] = __uint_as_float(b.u3);
     }
-    float pr[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) pr[i] = vq * u[i];
     if (!(bs <= 0 && be >= kBatch)) {
-        // position of posting i of this lane: 2 * lane + 128 * (i / 2) + i % 2
-        const uint32_t rel = (uint32_t)(2 * lane - bs), n = (uint32_t)(be - bs);
+        // position of posting i of this lane: 4 * lane + i
+        const uint32_t rel = (uint32_t)(4 * lane - bs), n = (uint32_t)(be - bs);
         const uint32_t spare = (uint32_t)(A.kt + lane);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (rel + 128 * (i / 2) + (i % 2) >= n) c[i] = spare;
+            if (rel + i >= n) c[i] = spare;
     }
     if (CB && test_flag) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if ((int)c[i] < A.kt && base + (int)c[i] >= A.nmv) pr[i] = 0.0f;
+            if ((int)c[i] < A.kt && base + (int)c[i] >= A.nmv) u[i] = 0.0f;
     }
     const float o0 = sim[c[0]], o1 = sim[c[1]], o2 = sim[c[2]], o3 = sim[c[3]];
-    sim[c[0]] = o0 + pr[0];
-    sim[c[1]] = o1 + pr[1];
-    sim[c[2]] = o2 + pr[2];
-    sim[c[3]] = o3 + pr[3];
+    sim[c[0]] = __builtin_fmaf(vq, u[0], o0);
+    sim[c[1]] = __builtin_fmaf(vq, u[1], o1);
+    sim[c[2]] = __builtin_fmaf(vq, u[2], o2);
+    sim[c[3]] = __builtin_fmaf(vq, u[3], o3);
 }
 
 // Dense head rows, accumulated in registers.  The head terms of a chunk are
@@ -180,14 +180,14 @@ __device__ inline void accumulate_batch(const WalkArgs& A, float* sim, const Bat
 // tile's centroids in order (two 16-byte loads per lane, term and group);
 // BF16 rows interleave each 512-centroid block so that one 16-byte load gives
 // a lane both of its 4-centroid groups.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHeadGroup = 512;   // centroids of one register-held group
 
 // bytes one wave's vector loads request (64 lanes x width), for the walk's
-// load counter: a list batch (ids + values), a record
-constexpr uint32_t kListBatchBytes32 = 2 * 256 + 2 * 512;
-constexpr uint32_t kListBatchBytes16 = 2 * 256 + 2 * 256;
+// load counter: a list batch (8-byte id loads; 16-byte FP32 or 8-byte BF16
+// value loads), a segment record (16-byte loads)
+constexpr uint32_t kListBatchBytes32 = 512 + 1024;
+constexpr uint32_t kListBatchBytes16 = 512 + 512;
 constexpr uint32_t kRecordBytes = 64 * 16;
 
 struct HAcc {
@@ -381,6 +381,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
 
     unsigned long long macc = 0, icp_cnt = 0, rel_cnt = 0;
     uint32_t lwords = 0;   // 4-byte words requested by this wave's vector loads (flushed at 2^31)
+    uint32_t hwords = 0;   // of which words of 16-byte-per-lane loads (head rows, records)
     const uint32_t xb = 4u + (A.x_f64 ? 8u : 4u);   // one staged term: column + value
     constexpr int kGrab = 8;
     for (int64_t g0 = wave_grab(work, kGrab); g0 < A.n; g0 = wave_grab(work, kGrab)) {
@@ -467,8 +468,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
             }
             lwords += (uint32_t)min(n, kTermCap) * (xb / 4);
             if (lwords >= 0x80000000u) {   // wave-uniform; far below any one object's share
-                if (lane == 0) atomicAdd(&A.counters[10], 4ull * lwords);
+                if (lane == 0) {
+                    atomicAdd(&A.counters[10], 4ull * lwords);
+        atomicAdd(&A.counters[11], 4ull * hwords);
+                    atomicAdd(&A.counters[11], 4ull * hwords);
+                }
                 lwords = 0;
+                hwords = 0;
             }
             // Work is a sequence of (tile, term chunk) pairs, tile-major; an
             // empty row still has one pair per tile so every tile is closed.
@@ -500,6 +506,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 nrec = A.rec[(int64_t)tl * A.d + (nin ? t : 0)];
                 nv = nin ? xv : 0.0f;
                 lwords += (kRecordBytes + (hb < kTermCap ? 0u : 64u * xb)) / 4;
+                hwords += kRecordBytes / 4;
             };
             seg_load(0);
             for (int pi = 0; pi < npairs; ++pi) {
@@ -538,7 +545,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                 const bool use_head = A.head && !(filt && CB);
                 if (use_head && h < n) hrow = hr;
                 const unsigned long long dl = ballot(hrow >= 0);
-                if (dl) lwords += head_terms<BF16>(A, sim, dl, hrow, v, tile, ktp, dlim, lane);
+                if (dl) {
+                    const uint32_t w = head_terms<BF16>(A, sim, dl, hrow, v, tile, ktp, dlim, lane);
+                    lwords += w;
+                    hwords += w;
+                }
                 // ---- other terms: structured lists
                 unsigned long long live = ballot(h < n && e > s0 && hrow < 0);
                 if (live) {
@@ -555,7 +566,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
                         const int64_t b0 = ls & ~(int64_t)7;
                         lo = (int)(ls - b0);
                         hi = (int)(bcast_i64(e, q) - b0);
-                        lwords += (uint32_t)((hi + kBatch - 1) / kBatch) * ((BF16 ? kListBatchBytes16 : kListBatchBytes32) / 4);
+                        {
+                            const uint32_t nbt = (uint32_t)((hi + kBatch - 1) / kBatch);
+                            lwords += nbt * ((BF16 ? kListBatchBytes16 : kListBatchBytes32) / 4);
+                            if (!BF16) hwords += nbt * (1024 / 4);   // the values' 16-byte loads
+                        }
                         lv = bcast_f32(v, q);
                         off = 0;
                         // extent rounded up to whole groups of 8 (the arrays keep
@@ -745,6 +760,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 6 : 
     if (lane == 0) {
         atomicAdd(&A.counters[0], macc);
         atomicAdd(&A.counters[10], 4ull * lwords);
+        atomicAdd(&A.counters[11], 4ull * hwords);
         atomicAdd(&A.counters[3], icp_cnt);
         if (rel_cnt) atomicAdd(&A.counters[7], rel_cnt);
     }
