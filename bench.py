@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 N_CU, CLOCK_GHZ = 256, 2.4   # MI355X compute units and peak engine clock
 POSTING_BYTES = {"fp32": 6, "bf16": 4}  # 2-byte centroid id + value
 WALK_KERNEL = "k_walk_fast<false, false>"   # FP32 postings, SIVF filter
-# counter-based DRAM-side traffic of the walk, written from rocprofv3 --pmc
+# bytes the walk's L2 sends toward memory, from calibrated rocprofv3 --pmc
 # runs; used only while the kernel sources still hash the same
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_8m_k10k_dram_traffic.md")
 WALK_SOURCES = ["paper_2103_16141_amd/csrc/k_assign.hip", "paper_2103_16141_amd/csrc/internal.h",
@@ -72,7 +72,6 @@ PROBE_CASES = [
     ("l1_b128", 0, 16, 16 << 10, 16 << 10, 16 << 10),
     ("l2_b128", 0, 16, 2 << 20, 256 << 10, 16 << 10),
     ("mall_b128", 0, 16, 64 << 20, 8 << 20, 256 << 10),
-    ("hbm_b128", 0, 16, 2 << 30, 64 << 20, 16 << 20),
     ("lds_read_b128", 1, 16, 0, 0, 0),
     ("lds_write_b128", 2, 16, 0, 0, 0),
 ]
@@ -312,6 +311,7 @@ def main():
     ap.add_argument("--tiles-per-launch", type=int, default=None,
                     help="centroid tiles per walk launch (default: library's, one tile per launch)")
     ap.add_argument("--skip-soft", action="store_true", help="skip the differentiation-form timing")
+    ap.add_argument("--soft-only", action="store_true", help="only time the differentiation form and print it")
     ap.add_argument("--filter", default="sivf", choices=["sivf", "ivf", "cbicp", "relaxed"],
                     help="ICP realisation: structured file (SIVF), none (IVF), per-posting test (IVF-CBICP), "
                          "SIVF with relaxed ICP")
@@ -330,6 +330,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.soft_only:
+        print(json.dumps(run_soft()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (one GPU per run).", file=sys.stderr)
@@ -403,13 +406,18 @@ def main():
     traffic = measured_traffic()
     dram = None
     if traffic:
-        dram_gbs = traffic["dram_bytes_per_launch"] / (traffic["launch_ms"] * 1e-3) / 1e9
-        dram = dict(bytes_per_launch=traffic["dram_bytes_per_launch"], gbs=dram_gbs,
+        # bytes the L2 sent toward memory per launch (reads + writes), from
+        # calibrated counters; memory-side-cache hits are included
+        tb = traffic["l2_to_memory_bytes_per_launch"]
+        dram_gbs = tb / (traffic["launch_ms"] * 1e-3) / 1e9
+        dram = dict(bytes_per_launch=tb, read_bytes_per_launch=traffic["read_bytes_per_launch"],
+                    write_bytes_per_launch=traffic["write_bytes_per_launch"], gbs=dram_gbs,
                     frac_of_measured_copy=dram_gbs / copy_gbs, frac_of_hbm_peak=dram_gbs / HBM_PEAK_GBS,
-                    profile=os.path.relpath(TRAFFIC_PROFILE, ROOT))
+                    includes_memory_side_cache_hits=traffic["includes_memory_side_cache_hits"],
+                    counter_launch_ms=traffic["launch_ms"], profile=os.path.relpath(TRAFFIC_PROFILE, ROOT))
     roofline = {"bound": "vmem", "achieved": achieved, "peak": peak, "unit": "GB/s",
                 "frac": achieved / peak if peak else None,
-                "traffic": traffic["dram_bytes_per_launch"] if traffic else None,
+                "traffic": traffic["l2_to_memory_bytes_per_launch"] if traffic else None,
                 "kernel": WALK_KERNEL, "launches": launches, "launch_avg_ms": launch_ms,
                 "bytes_per_launch": s32["walk_loaded_bytes"] / launches,
                 "wide_load_fraction": s32["walk_wide_bytes"] / s32["walk_loaded_bytes"],

@@ -38,10 +38,10 @@ def test_traffic_profile_used_only_for_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "traffic.md"
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
     assert bench.measured_traffic() is None                      # no profile
-    prof.write_text('text\nTRAFFIC_JSON {"walk_source_hash": "%s", "dram_bytes_per_launch": 123.5, '
+    prof.write_text('text\nTRAFFIC_JSON {"walk_source_hash": "%s", "l2_to_memory_bytes_per_launch": 123.5, '
                     '"launch_ms": 2.0}\n' % h)
-    assert bench.measured_traffic()["dram_bytes_per_launch"] == 123.5
-    prof.write_text('TRAFFIC_JSON {"walk_source_hash": "0000000000000000", "dram_bytes_per_launch": 123.5}\n')
+    assert bench.measured_traffic()["l2_to_memory_bytes_per_launch"] == 123.5
+    prof.write_text('TRAFFIC_JSON {"walk_source_hash": "0000000000000000", "l2_to_memory_bytes_per_launch": 1}\n')
     assert bench.measured_traffic() is None                      # taken on other kernel sources
     prof.write_text('TRAFFIC_JSON {not json}\n')
     assert bench.measured_traffic() is None
