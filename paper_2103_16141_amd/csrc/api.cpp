@@ -1076,6 +1076,7 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
     int64_t *cnt = nullptr, *colptr = nullptr, *sws = nullptr;
     int32_t *hist = nullptr, *xt_row = nullptr;
     float* xt_val = nullptr;
+    DctWs dw{};
     if (dC_out) {
         const int64_t nb = (n + 1023) / 1024;
         STCHK(ws(ctx, "soft_dCT", (int64_t)k * d, &dCT));
@@ -1086,6 +1087,28 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         STCHK(ws(ctx, "csc_val", std::max<int64_t>(Xc.nnz, 1), &xt_val));
         STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(d + 1, n + 1)) + 8, &sws));
         HIPCHK(ctx, soft_csc(n, d, Xc.nnz, Xc.rp, Xc.col, (const float*)Xc.val, hist, cnt, colptr, sws, xt_row, xt_val, s));
+        // the largest chunk's nonzeros bound the pieces of the dC pass; the
+        // piece length grows past 256 rows only to keep the partial rows
+        // within 512 MiB
+        const int64_t nch = std::max<int64_t>(1, (n + rc - 1) / rc);
+        int64_t* offs = nullptr;
+        STCHK(ws(ctx, "soft_offs", nch + 1, &offs));
+        HIPCHK(ctx, soft_chunk_offsets(Xc.rp, n, rc, nch, offs, s));
+        std::vector<int64_t> ho((size_t)nch + 1);
+        HIPCHK(ctx, hipMemcpyAsync(ho.data(), offs, (size_t)(nch + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        int64_t nnz_max = 0;
+        for (int64_t j = 0; j < nch; ++j) nnz_max = std::max(nnz_max, ho[(size_t)j + 1] - ho[(size_t)j]);
+        const int64_t cap = 512ll << 20;
+        dw.piece = std::max<int64_t>(256, (2 * nnz_max * (int64_t)k * 4 + cap - 1) / cap);
+        dw.max_pieces = 2 * nnz_max / dw.piece + 1;
+        STCHK(ws(ctx, "dct_lo", d, &dw.lo));
+        STCHK(ws(ctx, "dct_hi", d, &dw.hi));
+        STCHK(ws(ctx, "dct_np", d, &dw.np));
+        STCHK(ws(ctx, "dct_pstart", d + 1, &dw.pstart));
+        dw.scan_ws = sws;
+        STCHK(ws(ctx, "dct_item", dw.max_pieces, &dw.item));
+        STCHK(ws(ctx, "dct_part", dw.max_pieces * (int64_t)k, &dw.part));
     }
     int first = 1;
     for (int64_t c0 = 0; c0 < n || first; c0 += rc) {
@@ -1093,7 +1116,7 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         if (c1 > c0)
             HIPCHK(ctx, soft_bwd_rows(c0, c1, Xc.rp, Xc.col, (const float*)Xc.val, CT, k, tau, grad_loss, lse, dS, dxv,
                                       ctx->n_cu, s));
-        if (dC_out) HIPCHK(ctx, soft_dct(d, k, c0, c1, first, colptr, xt_row, xt_val, dS, dCT, ctx->n_cu, s));
+        if (dC_out) HIPCHK(ctx, soft_dct(d, k, c0, c1, first, colptr, xt_row, xt_val, dS, dCT, dw, ctx->n_cu, s));
         first = 0;
         if (c1 >= n) break;
     }

@@ -185,104 +185,226 @@ hipError_t soft_forward(int64_t N, const int64_t* rp, const int32_t* col, const 
 
 // ---------------------------------------------------------------- backward, rows of one chunk
 // For rows [c0, c1): recompute S, write dS (row-major, k columns) and dX on the
-// row's nonzeros.  dX: 16 terms at a time, each thread forms 16 partial dots
-// over its columns, partials go through LDS, 16 lanes per term finish the sum.
+// row's nonzeros, reading each gathered C^T value once.
+//
+// A workgroup owns a row and walks its columns in blocks of W.  For a block it
+// stages the row's C^T slices (W floats per term, kBwTerms terms per batch) in
+// LDS, then
+//   S:  thread (c, h) sums the h-th of 256 / W contiguous ranges of the terms
+//       for column c (in term order), and the ranges' sums are added in order;
+//   dS: -g exp(S / tau - lse) / tau, written out and kept in LDS;
+//   dX: thread j dots dS with term j's slice (columns in order, four
+//       interleaved partial sums added in a fixed order) and adds the block's
+//       dot to its running dX_j, blocks in column order.
+// Rows with more than kBwTerms terms stage their terms batch by batch and
+// gather each batch a second time for dX.  Rows are W + 4 floats apart, so a
+// term's slice and dS are read 16 bytes at a time in the dX pass; the S pass
+// reads consecutive columns.  W = 64 and 136 terms keep the LDS of a
+// workgroup under 40 KB, four workgroups per CU.
+// Workgroup barrier for data exchanged through LDS only: waits for the
+// wave's LDS operations, not for its global loads and stores, so gathers for
+// the next block and the dS row stores stay in flight across it.
+__device__ inline void bw_bar() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kBwTerms = 136;
+constexpr int kBwPre = 8;   // float4 gathers per thread in flight
+
+template <int W>
+struct BwLds {
+    static constexpr int kS = kSoftThreads / W;   // threads per column in the S pass
+    static constexpr int kStride = W + 4;          // floats between two terms' slices
+    alignas(16) float L[kBwTerms * kStride];
+    alignas(16) float P[kS][W];
+    alignas(16) float D[W];
+    int32_t t[kBwTerms];
+    float v[kBwTerms];
+};
+
+// term ids and values of entries [t0, t0 + m) of the row
+template <int W>
+__device__ inline void bw_stage_terms(BwLds<W>& sh, const int32_t* __restrict__ col, const float* __restrict__ xv,
+                                      int64_t r0, int t0, int m) {
+    for (int e = threadIdx.x; e < m; e += kSoftThreads) {
+        sh.t[e] = col[r0 + t0 + e];
+        sh.v[e] = xv[r0 + t0 + e];
+    }
+}
+
+// g[u] = C^T[t_e][cb + 4q .. +3] for slot e = e0 + u * 256 + tid (e = term * W/4 + q).
+// The 16-byte path and the element path are separate loops, so the former
+// stays one 16-byte load per slot.
+template <int W>
+__device__ inline void bw_gather(const BwLds<W>& sh, const float* __restrict__ CT, int32_t k, int64_t cb, int m,
+                                 int e0, float4 (&g)[kBwPre]) {
+    constexpr int per = W / 4;
+    const int tot = m * per;
+    if ((k & 3) == 0 && cb + W <= k) {
+        // the slots' term ids first (one LDS wait), then the loads
+        int32_t tt[kBwPre];
+#pragma unroll
+        for (int u = 0; u < kBwPre; ++u) {
+            const int e = min(e0 + u * kSoftThreads + (int)threadIdx.x, tot - 1);
+            tt[u] = sh.t[e / per];
+        }
+#pragma unroll
+        for (int u = 0; u < kBwPre; ++u) {
+            const int e = e0 + u * kSoftThreads + threadIdx.x;
+            g[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (e < tot) g[u] = *reinterpret_cast<const float4*>(CT + (int64_t)tt[u] * k + cb + 4 * (e % per));
+        }
+    } else {
+        for (int u = 0; u < kBwPre; ++u) {
+            const int e = e0 + u * kSoftThreads + threadIdx.x;
+            g[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (e < tot) {
+                const float* src = CT + (int64_t)sh.t[e / per] * k + cb + 4 * (e % per);
+                const int64_t c = cb + 4 * (e % per);
+                g[u].x = c + 0 < k ? src[0] : 0.0f;
+                g[u].y = c + 1 < k ? src[1] : 0.0f;
+                g[u].z = c + 2 < k ? src[2] : 0.0f;
+                g[u].w = c + 3 < k ? src[3] : 0.0f;
+            }
+        }
+    }
+}
+
+template <int W>
+__device__ inline void bw_put(BwLds<W>& sh, int m, int e0, const float4 (&g)[kBwPre]) {
+    constexpr int per = W / 4;
+    const int tot = m * per;
+#pragma unroll
+    for (int u = 0; u < kBwPre; ++u) {
+        const int e = e0 + u * kSoftThreads + threadIdx.x;
+        if (e < tot) *reinterpret_cast<float4*>(sh.L + (e / per) * BwLds<W>::kStride + 4 * (e % per)) = g[u];
+    }
+}
+
+// L[e][c] = C^T[t_e][cb + c] for e < m, c < W (columns >= k read as 0)
+template <int W>
+__device__ inline void bw_stage_slices(BwLds<W>& sh, const float* __restrict__ CT, int32_t k, int64_t cb, int m) {
+    const int tot = m * (W / 4);
+    for (int e0 = 0; e0 < tot; e0 += kBwPre * kSoftThreads) {
+        float4 g[kBwPre];
+        bw_gather<W>(sh, CT, k, cb, m, e0, g);
+        bw_put<W>(sh, m, e0, g);
+    }
+}
+
+// dot of D[0..w) with L row j, four interleaved partial sums in a fixed order
+// (D is zero past w and the slice's loaded columns, so whole groups of 4 are
+// summed; columns past w in the slice are zero too)
+template <int W>
+__device__ inline float bw_dot(const BwLds<W>& sh, int j, int w) {
+    const float* row = sh.L + j * BwLds<W>::kStride;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int c = 0; c < w; c += 4) {
+        const float4 r = *reinterpret_cast<const float4*>(row + c);
+        const float4 d = *reinterpret_cast<const float4*>(sh.D + c);
+        a0 = fmaf(d.x, r.x, a0);
+        a1 = fmaf(d.y, r.y, a1);
+        a2 = fmaf(d.z, r.z, a2);
+        a3 = fmaf(d.w, r.w, a3);
+    }
+    return (a0 + a1) + (a2 + a3);
+}
+
+// S of the staged terms [0, m) for column c, partial range h, then the block's
+// dS (written to dsrow and D); all threads take part
+template <int W>
+__device__ inline float bw_s_partial(const BwLds<W>& sh, int m, int c, int h) {
+    constexpr int kS = BwLds<W>::kS;
+    const int q = (m + kS - 1) / kS;
+    const int lo = min(m, h * q), hi = min(m, lo + q);
+    float s = 0.0f;
+    for (int e = lo; e < hi; ++e) s = fmaf(sh.v[e], sh.L[e * BwLds<W>::kStride + c], s);
+    return s;
+}
+
+template <int W>
+__device__ inline void bw_ds(BwLds<W>& sh, float s, int c, int h, int w, float inv_tau, float neg_g_over_tau, float l,
+                             float* dsrow, int64_t cb) {
+    constexpr int kS = BwLds<W>::kS;
+    sh.P[h][c] = s;
+    bw_bar();
+    if (h == 0) {
+        float st = sh.P[0][c];
+#pragma unroll
+        for (int r = 1; r < kS; ++r) st = st + sh.P[r][c];
+        const float ds = c < w ? neg_g_over_tau * expf(st * inv_tau - l) : 0.0f;
+        sh.D[c] = ds;
+        if (c < w) dsrow[cb + c] = ds;
+    }
+    bw_bar();
+}
+
+template <int W>
 __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* __restrict__ rp,
                                                                 const int32_t* __restrict__ col,
                                                                 const float* __restrict__ xv,
                                                                 const float* __restrict__ CT, int32_t k, float inv_tau,
                                                                 float neg_g_over_tau, const float* __restrict__ lse,
                                                                 float* __restrict__ dS, float* __restrict__ dxv) {
-    __shared__ int32_t s_t[kSoftTermsInLds];
-    __shared__ float s_v[kSoftTermsInLds];
-    __shared__ float part[16][kSoftThreads + 1];
-    const int lane = threadIdx.x & 63;
+    __shared__ BwLds<W> sh;
+    const int c = threadIdx.x % W, h = threadIdx.x / W;
     for (int64_t i = c0 + blockIdx.x; i < c1; i += gridDim.x) {
         const int64_t r0 = rp[i];
         const int n = (int)(rp[i + 1] - r0);
+        const int nb = (n + kBwTerms - 1) / kBwTerms;
         const float l = lse[i];
         float* dsrow = dS + (i - c0) * (int64_t)k;
-        for (int64_t ch0 = 0; ch0 < k; ch0 += kSoftChunk) {
-            float acc[kSoftCols];
-            soft_row_chunk(r0, n, col, xv, CT, k, ch0, acc, s_t, s_v);
-            float ds[kSoftCols];
-#pragma unroll
-            for (int q = 0; q < kSoftCols; ++q) {
-                const int64_t c = ch0 + soft_col(q);
-                ds[q] = c < k ? neg_g_over_tau * expf(acc[q] * inv_tau - l) : 0.0f;
-                if (c < k) dsrow[c] = ds[q];
+        bw_bar();
+        if (nb == 1) bw_stage_terms<W>(sh, col, xv, r0, 0, n);
+        float dxr = 0.0f;   // dX of term threadIdx.x (one batch only)
+        for (int64_t cb = 0; cb < k; cb += W) {
+            const int w = (int)min((int64_t)W, k - cb);
+            float s = 0.0f;
+            for (int b = 0; b < nb; ++b) {
+                const int t0 = b * kBwTerms, m = min(kBwTerms, n - t0);
+                bw_bar();
+                if (nb > 1) {
+                    bw_stage_terms<W>(sh, col, xv, r0, t0, m);
+                    bw_bar();
+                }
+                bw_stage_slices<W>(sh, CT, k, cb, m);
+                bw_bar();
+                s += bw_s_partial<W>(sh, m, c, h);
             }
-            // dX contribution of this column chunk
-            const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
-            for (int h0 = 0; h0 < n; h0 += 16) {
-                const int m = min(16, n - h0);
-                float pd[16];
-                if (full) {
-                    // four terms' rows in flight, then their dots in column order
-#pragma unroll
-                    for (int e0 = 0; e0 < 16; e0 += 4) {
-                        float4 g[4][4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int e = e0 + u;
-                            const float* row = CT + (int64_t)col[r0 + h0 + (e < m ? e : 0)] * k + ch0;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                g[u][q] = *reinterpret_cast<const float4*>(row + q * (kSoftThreads * 4) + threadIdx.x * 4);
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            float a = 0.0f;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                a = fmaf(ds[4 * q + 0], g[u][q].x, a);
-                                a = fmaf(ds[4 * q + 1], g[u][q].y, a);
-                                a = fmaf(ds[4 * q + 2], g[u][q].z, a);
-                                a = fmaf(ds[4 * q + 3], g[u][q].w, a);
-                            }
-                            pd[e0 + u] = e0 + u < m ? a : 0.0f;
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        pd[e] = 0.0f;
-                        if (e < m) {
-                            const float* row = CT + (int64_t)col[r0 + h0 + e] * k + ch0;
-#pragma unroll
-                            for (int q = 0; q < kSoftCols; ++q)
-                                if (ch0 + soft_col(q) < k) pd[e] = fmaf(ds[q], row[soft_col(q)], pd[e]);
-                        }
+            bw_ds<W>(sh, s, c, h, w, inv_tau, neg_g_over_tau, l, dsrow, cb);
+            if (nb == 1) {
+                if (threadIdx.x < n) dxr += bw_dot<W>(sh, threadIdx.x, w);
+            } else {
+                for (int b = 0; b < nb; ++b) {
+                    const int t0 = b * kBwTerms, m = min(kBwTerms, n - t0);
+                    bw_bar();
+                    bw_stage_terms<W>(sh, col, xv, r0, t0, m);
+                    bw_bar();
+                    bw_stage_slices<W>(sh, CT, k, cb, m);
+                    bw_bar();
+                    if (threadIdx.x < m) {
+                        const int64_t p = r0 + t0 + threadIdx.x;
+                        dxv[p] = (cb == 0 ? 0.0f : dxv[p]) + bw_dot<W>(sh, threadIdx.x, w);
                     }
                 }
-                __syncthreads();
-#pragma unroll
-                for (int e = 0; e < 16; ++e) part[e][threadIdx.x] = pd[e];
-                __syncthreads();
-                // thread -> (term e = tid / 16, slice r = tid % 16) sums 16 partials, then 16 lanes reduce
-                const int e = threadIdx.x >> 4, r = threadIdx.x & 15;
-                float s2 = 0.0f;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) s2 += part[e][r * 16 + q];
-#pragma unroll
-                for (int o = 8; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
-                if (r == 0 && e < m) {
-                    const int64_t p = r0 + h0 + e;
-                    dxv[p] = (ch0 == 0 ? 0.0f : dxv[p]) + s2;
-                }
-                (void)lane;
             }
         }
+        if (nb == 1 && threadIdx.x < n) dxv[r0 + threadIdx.x] = dxr;
     }
 }
+
+constexpr int kBwW = 64;   // columns per block of the rows pass
 
 hipError_t soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* rp, const int32_t* col, const float* xv,
                          const float* CT, int32_t k, float tau, float grad, const float* lse, float* dS, float* dxv,
                          int n_cu, hipStream_t s) {
-    int64_t grid = std::min<int64_t>(c1 - c0, (int64_t)n_cu * 8);
+    const int per_cu = (int)(160 * 1024 / sizeof(BwLds<kBwW>));
+    int64_t grid = std::min<int64_t>(c1 - c0, (int64_t)n_cu * std::max(per_cu, 1));
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_soft_bwd_rows, dim3((unsigned)grid), dim3(kSoftThreads), 0, s, c0, c1, rp, col, xv, CT, k,
-                       1.0f / tau, -grad / tau, lse, dS, dxv);
+    hipLaunchKernelGGL((k_soft_bwd_rows<kBwW>), dim3((unsigned)grid), dim3(kSoftThreads), 0, s, c0, c1,
+                       rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxv);
     return hipGetLastError();
 }
 
@@ -353,36 +475,133 @@ hipError_t soft_csc(int64_t N, int64_t d, int64_t nnz, const int64_t* rp, const 
 }
 
 // ---------------------------------------------------------------- dC^T, term-major, one chunk of rows
-// dCT[t][:] (+)= sum over rows i in [c0, c1) containing t, ascending, of v_it * dS[i - c0][:]
-__global__ __launch_bounds__(kSoftThreads) void k_soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first,
-                                                           const int64_t* __restrict__ colptr,
-                                                           const int32_t* __restrict__ xt_row,
-                                                           const float* __restrict__ xt_val,
-                                                           const float* __restrict__ dS, float* __restrict__ dCT) {
+// dCT[t][:] (+)= sum over rows i in [c0, c1) containing t, ascending, of v_it * dS[i - c0][:].
+//
+// A term's rows inside the chunk are the range [lo_t, hi_t) of its ascending
+// CSC list.  Zipf term frequencies make a few ranges as long as the chunk
+// (the hottest terms occur in nearly every row) while most hold a handful of
+// rows, so one workgroup per term would leave the long ranges to a few
+// workgroups.  Ranges of at most `piece` rows are summed by one workgroup
+// straight into dCT[t]; longer ones are cut into pieces of `piece` rows, each
+// summed by its own workgroup into a partial row, and the partial rows are
+// then added into dCT[t] piece by piece in ascending order.  Every sum has a
+// fixed order, so the result is run-to-run identical.  A long range of len
+// rows has ceil(len / piece) < 2 len / piece pieces, so a chunk with nnz_c
+// nonzeros has fewer than 2 nnz_c / piece of them: the host sizes the partial
+// rows and the piece length from that bound.
+
+// lo/hi of every term's rows inside [c0, c1); np[t] = pieces of a long range (else 0)
+__global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, const int64_t* __restrict__ colptr,
+                           const int32_t* __restrict__ xt_row, int64_t* __restrict__ lo_out,
+                           int64_t* __restrict__ hi_out, int64_t* __restrict__ np) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    const int64_t b = colptr[t], e = colptr[t + 1];
+    int64_t lo = b, len = e - b;
+    while (len > 0) {
+        const int64_t half = len >> 1;
+        if (xt_row[lo + half] < c0) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    int64_t hi = lo;
+    len = e - lo;
+    while (len > 0) {
+        const int64_t half = len >> 1;
+        if (xt_row[hi + half] < c1) {
+            hi += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    lo_out[t] = lo;
+    hi_out[t] = hi;
+    np[t] = hi - lo > piece ? (hi - lo + piece - 1) / piece : 0;
+}
+
+// item[pstart[t] + j] = t for the pieces j of each long range
+__global__ void k_dct_items(int64_t d, int64_t max_pieces, const int64_t* __restrict__ np,
+                            const int64_t* __restrict__ pstart, int32_t* __restrict__ item) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    const int64_t e = min(pstart[t] + np[t], max_pieces);
+    for (int64_t q = pstart[t]; q < e; ++q) item[q] = (int32_t)t;
+}
+
+__global__ void k_chunk_offsets(const int64_t* __restrict__ rp, int64_t n, int64_t rc, int64_t nch,
+                                int64_t* __restrict__ out) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j <= nch) out[j] = rp[min(j * rc, n)];
+}
+
+hipError_t soft_chunk_offsets(const int64_t* rp, int64_t n, int64_t rc, int64_t nch, int64_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_offsets, dim3((unsigned)((nch + 256) / 256)), dim3(256), 0, s, rp, n, rc, nch, out);
+    return hipGetLastError();
+}
+
+// acc[q] (+)= sum over CSC entries [p0, p1) (rows ascending) of v * dS row
+__device__ inline void dct_sum(int32_t k, int64_t c0, int64_t ch0, int64_t p0, int64_t p1,
+                               const int32_t* __restrict__ xt_row, const float* __restrict__ xt_val,
+                               const float* __restrict__ dS, float acc[kSoftCols]) {
+    const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
+    if (full) {
+        // kDctRows rows per step: their ids, then all their gathers, are issued
+        // before the first multiply-add, which still runs in ascending row order
+        for (int64_t q0 = p0; q0 < p1; q0 += kDctRows) {
+            const int m = (int)min((int64_t)kDctRows, p1 - q0);
+            int64_t ro[kDctRows];
+            float vv[kDctRows];
+#pragma unroll
+            for (int u = 0; u < kDctRows; ++u) {
+                const bool in = u < m;
+                ro[u] = (int64_t)(xt_row[in ? q0 + u : q0] - c0) * k + ch0;
+                vv[u] = in ? xt_val[q0 + u] : 0.0f;
+            }
+            float4 g[kDctRows][4];
+#pragma unroll
+            for (int u = 0; u < kDctRows; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    g[u][q] = *reinterpret_cast<const float4*>(dS + ro[u] + q * (kSoftThreads * 4) + threadIdx.x * 4);
+#pragma unroll
+            for (int u = 0; u < kDctRows; ++u) {
+                if (u < m) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc[4 * q + 0] = fmaf(vv[u], g[u][q].x, acc[4 * q + 0]);
+                        acc[4 * q + 1] = fmaf(vv[u], g[u][q].y, acc[4 * q + 1]);
+                        acc[4 * q + 2] = fmaf(vv[u], g[u][q].z, acc[4 * q + 2]);
+                        acc[4 * q + 3] = fmaf(vv[u], g[u][q].w, acc[4 * q + 3]);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int64_t p = p0; p < p1; ++p) {
+            const float v = xt_val[p];
+            const float* row = dS + (int64_t)(xt_row[p] - c0) * k + ch0;
+#pragma unroll
+            for (int q = 0; q < kSoftCols; ++q)
+                if (ch0 + soft_col(q) < k) acc[q] = fmaf(v, row[soft_col(q)], acc[q]);
+        }
+    }
+}
+
+// short ranges: one workgroup per term, straight into dCT[t] (zeroed on the
+// first chunk when the term has no row in it)
+__global__ __launch_bounds__(kSoftThreads) void k_dct_short(int64_t d, int32_t k, int64_t c0, int first, int64_t piece,
+                                                            const int64_t* __restrict__ lo_t,
+                                                            const int64_t* __restrict__ hi_t,
+                                                            const int32_t* __restrict__ xt_row,
+                                                            const float* __restrict__ xt_val,
+                                                            const float* __restrict__ dS, float* __restrict__ dCT) {
     for (int64_t t = blockIdx.x; t < d; t += gridDim.x) {
-        const int64_t b = colptr[t], e = colptr[t + 1];
-        // rows of this chunk: [lo, hi) inside the ascending list
-        int64_t lo = b, len = e - b;
-        while (len > 0) {
-            const int64_t half = len >> 1;
-            if (xt_row[lo + half] < c0) {
-                lo += half + 1;
-                len -= half + 1;
-            } else {
-                len = half;
-            }
-        }
-        int64_t hi = lo;
-        len = e - lo;
-        while (len > 0) {
-            const int64_t half = len >> 1;
-            if (xt_row[hi + half] < c1) {
-                hi += half + 1;
-                len -= half + 1;
-            } else {
-                len = half;
-            }
-        }
+        const int64_t lo = lo_t[t], hi = hi_t[t];
+        if (hi - lo > piece) continue;   // a long range: summed in pieces
         if (lo == hi && !first) continue;
         for (int64_t ch0 = 0; ch0 < k; ch0 += kSoftChunk) {
             float acc[kSoftCols];
@@ -392,50 +611,7 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_dct(int64_t d, int32_t k,
                 const int64_t c = ch0 + soft_col(q);
                 acc[q] = (first || c >= k) ? 0.0f : out[soft_col(q)];
             }
-            const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
-            if (full) {
-                // kDctRows rows per step: their ids, then all their gathers, are
-                // issued before the first multiply-add, which still runs in
-                // ascending row order
-                for (int64_t p0 = lo; p0 < hi; p0 += kDctRows) {
-                    const int m = (int)min((int64_t)kDctRows, hi - p0);
-                    int64_t ro[kDctRows];
-                    float vv[kDctRows];
-#pragma unroll
-                    for (int u = 0; u < kDctRows; ++u) {
-                        const bool in = u < m;
-                        ro[u] = (int64_t)(xt_row[in ? p0 + u : p0] - c0) * k + ch0;
-                        vv[u] = in ? xt_val[p0 + u] : 0.0f;
-                    }
-                    float4 g[kDctRows][4];
-#pragma unroll
-                    for (int u = 0; u < kDctRows; ++u)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            g[u][q] = *reinterpret_cast<const float4*>(dS + ro[u] + q * (kSoftThreads * 4) +
-                                                                      threadIdx.x * 4);
-#pragma unroll
-                    for (int u = 0; u < kDctRows; ++u) {
-                        if (u < m) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                acc[4 * q + 0] = fmaf(vv[u], g[u][q].x, acc[4 * q + 0]);
-                                acc[4 * q + 1] = fmaf(vv[u], g[u][q].y, acc[4 * q + 1]);
-                                acc[4 * q + 2] = fmaf(vv[u], g[u][q].z, acc[4 * q + 2]);
-                                acc[4 * q + 3] = fmaf(vv[u], g[u][q].w, acc[4 * q + 3]);
-                            }
-                        }
-                    }
-                }
-            } else {
-                for (int64_t p = lo; p < hi; ++p) {
-                    const float v = xt_val[p];
-                    const float* row = dS + (int64_t)(xt_row[p] - c0) * k + ch0;
-#pragma unroll
-                    for (int q = 0; q < kSoftCols; ++q)
-                        if (ch0 + soft_col(q) < k) acc[q] = fmaf(v, row[soft_col(q)], acc[q]);
-                }
-            }
+            dct_sum(k, c0, ch0, lo, hi, xt_row, xt_val, dS, acc);
 #pragma unroll
             for (int q = 0; q < kSoftCols; ++q)
                 if (ch0 + soft_col(q) < k) out[soft_col(q)] = acc[q];
@@ -443,11 +619,76 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_dct(int64_t d, int32_t k,
     }
 }
 
+// one piece of a long range into its partial row
+__global__ __launch_bounds__(kSoftThreads) void k_dct_piece(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
+                                                            int64_t piece,
+                                                            const int32_t* __restrict__ item,
+                                                            const int64_t* __restrict__ pstart,
+                                                            const int64_t* __restrict__ lo_t,
+                                                            const int64_t* __restrict__ hi_t,
+                                                            const int32_t* __restrict__ xt_row,
+                                                            const float* __restrict__ xt_val,
+                                                            const float* __restrict__ dS, float* __restrict__ part) {
+    const int64_t npieces = min(pstart[d], max_pieces);   // the host bound caps the device count
+    for (int64_t q = blockIdx.x; q < npieces; q += gridDim.x) {
+        const int32_t t = item[q];
+        const int64_t j = q - pstart[t];
+        const int64_t p0 = lo_t[t] + j * piece, p1 = min(hi_t[t], p0 + piece);
+        for (int64_t ch0 = 0; ch0 < k; ch0 += kSoftChunk) {
+            float acc[kSoftCols];
+#pragma unroll
+            for (int qq = 0; qq < kSoftCols; ++qq) acc[qq] = 0.0f;
+            dct_sum(k, c0, ch0, p0, p1, xt_row, xt_val, dS, acc);
+            float* out = part + q * (int64_t)k + ch0;
+#pragma unroll
+            for (int qq = 0; qq < kSoftCols; ++qq)
+                if (ch0 + soft_col(qq) < k) out[soft_col(qq)] = acc[qq];
+        }
+    }
+}
+
+// dCT[t] = (first ? 0 : dCT[t]) + partial rows of t's pieces, in piece order;
+// one workgroup per long-range term (found at its first piece), threads over columns
+__global__ void k_dct_combine(int64_t d, int64_t max_pieces, int32_t k, int first, const int32_t* __restrict__ item,
+                              const int64_t* __restrict__ np, const int64_t* __restrict__ pstart,
+                              const float* __restrict__ part, float* __restrict__ dCT) {
+    const int64_t npieces = min(pstart[d], max_pieces);
+    for (int64_t q = blockIdx.x; q < npieces; q += gridDim.x) {
+        const int32_t t = item[q];
+        if (pstart[t] != q) continue;   // not the term's first piece
+        const int64_t m = np[t];
+        if (q + m > max_pieces) continue;   // cannot happen: the host bound holds
+        const float* pr = part + q * (int64_t)k;
+        for (int64_t c = threadIdx.x; c < k; c += blockDim.x) {
+            float acc = first ? 0.0f : dCT[t * (int64_t)k + c];
+            for (int64_t j = 0; j < m; ++j) acc = acc + pr[j * (int64_t)k + c];
+            dCT[t * (int64_t)k + c] = acc;
+        }
+    }
+}
+
 hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, const int64_t* colptr,
-                    const int32_t* xt_row, const float* xt_val, const float* dS, float* dCT, int n_cu, hipStream_t s) {
-    int64_t grid = std::min<int64_t>(d, (int64_t)n_cu * 16);
-    hipLaunchKernelGGL(k_soft_dct, dim3((unsigned)grid), dim3(kSoftThreads), 0, s, d, k, c0, c1, first, colptr, xt_row,
-                       xt_val, dS, dCT);
+                    const int32_t* xt_row, const float* xt_val, const float* dS, float* dCT, DctWs w, int n_cu,
+                    hipStream_t s) {
+    if (d <= 0) return hipSuccess;
+    const unsigned tb = (unsigned)((d + 255) / 256);
+    hipLaunchKernelGGL(k_dct_plan, dim3(tb), dim3(256), 0, s, d, c0, c1, w.piece, colptr, xt_row, w.lo, w.hi, w.np);
+    hipError_t e = exclusive_scan_i64(w.np, w.pstart, d, w.scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dct_items, dim3(tb), dim3(256), 0, s, d, w.max_pieces, w.np, w.pstart, w.item);
+    const int64_t grid = std::min<int64_t>(d, (int64_t)n_cu * 16);
+    hipLaunchKernelGGL(k_dct_short, dim3((unsigned)grid), dim3(kSoftThreads), 0, s, d, k, c0, first, w.piece, w.lo,
+                       w.hi,
+                       xt_row, xt_val, dS, dCT);
+    // pieces: at most max_pieces (a bound from the chunk's nonzeros), the
+    // exact count is pstart[d] on the device
+    if (w.max_pieces > 0) {
+        const int64_t pg = std::min<int64_t>(w.max_pieces, (int64_t)n_cu * 16);
+        hipLaunchKernelGGL(k_dct_piece, dim3((unsigned)pg), dim3(kSoftThreads), 0, s, d, w.max_pieces, k, c0, w.piece,
+                           w.item, w.pstart, w.lo, w.hi, xt_row, xt_val, dS, w.part);
+        hipLaunchKernelGGL(k_dct_combine, dim3((unsigned)pg), dim3(256), 0, s, d, w.max_pieces, k, first, w.item, w.np,
+                           w.pstart, w.part, dCT);
+    }
     return hipGetLastError();
 }
 

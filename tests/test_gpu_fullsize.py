@@ -353,6 +353,17 @@ def test_soft_fullsize_sampled():
     dc_ref, _ = oracle.soft_backward(corpus, C64, tau, g, lse_t, rows=rows_t, want_dx=False)
     for t in terms:
         np.testing.assert_allclose(dC_h[:, t], dc_ref[:, t], rtol=2e-3, atol=1e-9)
+    # one term with ~300 rows in each 16,384-row chunk of the backward: its
+    # chunk ranges are summed in pieces and combined
+    cand = np.nonzero((df >= 4500) & (df <= 6500))[0]
+    assert len(cand) > 0
+    t = int(rng.choice(cand))
+    pos = np.nonzero(corpus.col == t)[0]
+    rows_t = np.unique(np.searchsorted(corpus.row_ptr, pos, side="right") - 1)
+    log("dC column of a term in %d rows" % len(rows_t))
+    lse_t = oracle.soft_forward(corpus, C64, tau, rows=rows_t)
+    dc_ref, _ = oracle.soft_backward(corpus, C64, tau, g, lse_t, rows=rows_t, want_dx=False)
+    np.testing.assert_allclose(dC_h[:, t], dc_ref[:, t], rtol=2e-3, atol=1e-9)
     assert math.isfinite(loss)
 
 

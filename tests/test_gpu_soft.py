@@ -39,7 +39,7 @@ def _ctx():
     return Context(0)
 
 
-@pytest.mark.parametrize("n,d,k", [(300, 500, 50), (257, 800, 5003), (1000, 3000, 4096)])
+@pytest.mark.parametrize("n,d,k", [(300, 500, 50), (257, 800, 5003), (1000, 3000, 4096), (4000, 1500, 20000)])
 def test_soft_forward_backward_match_oracle(n, d, k):
     log("soft n=%d d=%d k=%d" % (n, d, k))
     c, C = _case(n, d, k, seed=n + k)
@@ -59,6 +59,25 @@ def test_soft_forward_backward_match_oracle(n, d, k):
     xs = np.zeros(d)
     np.add.at(xs, c.col, c.val.astype(np.float64))
     np.testing.assert_allclose(dC.cpu().numpy().astype(np.float64).sum(0), -(g / TAU) * xs, rtol=2e-3, atol=1e-6)
+
+
+@pytest.mark.parametrize("k", [300, 299])
+def test_soft_rows_longer_than_one_lds_batch(k):
+    # ~300 terms per row: the backward stages a row's centroid slices in
+    # batches of 144 terms (two or three per row); k = 300 ends on a partial
+    # 128-column block, k = 299 also takes the unaligned gathers
+    log("soft long rows k=%d" % k)
+    c, C = _case(120, 2000, k, seed=77 + k, lam=300)
+    assert np.diff(c.row_ptr).max() > 288
+    X, Cg = _dev(c, C)
+    ctx = _ctx()
+    lse, _ = ctx.soft_assign_fwd(X, Cg, TAU)
+    lse_ref = oracle.soft_forward(c, C.astype(np.float64), TAU)
+    np.testing.assert_allclose(lse.cpu().numpy(), lse_ref, rtol=0, atol=5e-4)
+    dC, dX = ctx.soft_assign_bwd(X, Cg, TAU, lse, 1.3)
+    dC_ref, dX_ref = oracle.soft_backward(c, C.astype(np.float64), TAU, 1.3, lse_ref)
+    np.testing.assert_allclose(dX.cpu().numpy(), dX_ref, rtol=2e-3, atol=1e-9)
+    np.testing.assert_allclose(dC.cpu().numpy(), dC_ref, rtol=2e-3, atol=1e-7)
 
 
 def test_soft_backward_is_deterministic_and_partial_outputs():
