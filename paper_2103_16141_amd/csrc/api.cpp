@@ -1038,13 +1038,16 @@ sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
     Csr Xc;
     STCHK(validate(ctx, X, &Xc));
     if (Xc.f64) return fail(ctx, SIVF_E_UNSUPPORTED, "soft assignment takes SIVF_F32 object values");
-    float* CT = nullptr;
+    float *CT = nullptr, *pmax = nullptr, *psum = nullptr;
     double* loss = nullptr;
     STCHK(ws(ctx, "soft_CT", (int64_t)k * Xc.d, &CT));
     STCHK(ws(ctx, "soft_loss", 1, &loss));
+    STCHK(ws(ctx, "soft_pmax", std::max<int64_t>(Xc.n, 1) * 8, &pmax));
+    STCHK(ws(ctx, "soft_psum", std::max<int64_t>(Xc.n, 1) * 8, &psum));
     hipStream_t s = ctx->stream;
     HIPCHK(ctx, soft_transpose(C, CT, k, Xc.d, s));
-    HIPCHK(ctx, soft_forward(Xc.n, Xc.rp, Xc.col, (const float*)Xc.val, CT, k, tau, lse_out, loss, ctx->n_cu, s));
+    HIPCHK(ctx, soft_forward(Xc.n, Xc.rp, Xc.col, (const float*)Xc.val, CT, k, tau, lse_out, loss, pmax, psum,
+                             ctx->n_cu, s));
     if (loss_host) {
         HIPCHK(ctx, hipMemcpyAsync(loss_host, loss, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1073,6 +1076,19 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
     STCHK(ws(ctx, "soft_dS", rc * (int64_t)k, &dS));
     if (!dxv) STCHK(ws(ctx, "soft_dx", std::max<int64_t>(Xc.nnz, 1), &dxv));
     HIPCHK(ctx, soft_transpose(C, CT, k, d, s));
+    // nonzero offsets of the row chunks: they size the per-group dX partials
+    // and bound the pieces of the dC pass
+    const int64_t nch = std::max<int64_t>(1, (n + rc - 1) / rc);
+    int64_t* offs = nullptr;
+    STCHK(ws(ctx, "soft_offs", nch + 1, &offs));
+    HIPCHK(ctx, soft_chunk_offsets(Xc.rp, n, rc, nch, offs, s));
+    std::vector<int64_t> ho((size_t)nch + 1);
+    HIPCHK(ctx, hipMemcpyAsync(ho.data(), offs, (size_t)(nch + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    int64_t nnz_max = 0;
+    for (int64_t j = 0; j < nch; ++j) nnz_max = std::max(nnz_max, ho[(size_t)j + 1] - ho[(size_t)j]);
+    float* dxp = nullptr;
+    STCHK(ws(ctx, "soft_dxp", std::max<int64_t>(nnz_max, 1) * 8, &dxp));
     int64_t *cnt = nullptr, *colptr = nullptr, *sws = nullptr;
     int32_t *hist = nullptr, *xt_row = nullptr;
     float* xt_val = nullptr;
@@ -1090,15 +1106,6 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         // the largest chunk's nonzeros bound the pieces of the dC pass; the
         // piece length grows past 256 rows only to keep the partial rows
         // within 512 MiB
-        const int64_t nch = std::max<int64_t>(1, (n + rc - 1) / rc);
-        int64_t* offs = nullptr;
-        STCHK(ws(ctx, "soft_offs", nch + 1, &offs));
-        HIPCHK(ctx, soft_chunk_offsets(Xc.rp, n, rc, nch, offs, s));
-        std::vector<int64_t> ho((size_t)nch + 1);
-        HIPCHK(ctx, hipMemcpyAsync(ho.data(), offs, (size_t)(nch + 1) * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        int64_t nnz_max = 0;
-        for (int64_t j = 0; j < nch; ++j) nnz_max = std::max(nnz_max, ho[(size_t)j + 1] - ho[(size_t)j]);
         const int64_t cap = 512ll << 20;
         dw.piece = std::max<int64_t>(256, (2 * nnz_max * (int64_t)k * 4 + cap - 1) / cap);
         dw.max_pieces = 2 * nnz_max / dw.piece + 1;
@@ -1111,11 +1118,11 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         STCHK(ws(ctx, "dct_part", dw.max_pieces * (int64_t)k, &dw.part));
     }
     int first = 1;
-    for (int64_t c0 = 0; c0 < n || first; c0 += rc) {
+    for (int64_t c0 = 0, j = 0; c0 < n || first; c0 += rc, ++j) {
         const int64_t c1 = std::min(n, c0 + rc);
         if (c1 > c0)
-            HIPCHK(ctx, soft_bwd_rows(c0, c1, Xc.rp, Xc.col, (const float*)Xc.val, CT, k, tau, grad_loss, lse, dS, dxv,
-                                      ctx->n_cu, s));
+            HIPCHK(ctx, soft_bwd_rows(c0, c1, ho[(size_t)j], ho[(size_t)j + 1], Xc.rp, Xc.col, (const float*)Xc.val, CT,
+                                      k, tau, grad_loss, lse, dS, dxp, dxv, ctx->n_cu, s));
         if (dC_out) HIPCHK(ctx, soft_dct(d, k, c0, c1, first, colptr, xt_row, xt_val, dS, dCT, dw, ctx->n_cu, s));
         first = 0;
         if (c1 >= n) break;

@@ -251,11 +251,13 @@ hipError_t upd_segsum(const Csr& X, int32_t k, const uint8_t* lam, int allow_cop
 
 // soft assignment
 hipError_t soft_transpose(const float* in, float* out, int64_t R, int64_t Cn, hipStream_t s);
+// pmax, psum: [N * 8] per-row partial max / sum-exp of the 8 column groups
 hipError_t soft_forward(int64_t N, const int64_t* rp, const int32_t* col, const float* xv, const float* CT, int32_t k,
-                        float tau, float* lse, double* loss_dev, int n_cu, hipStream_t s);
-hipError_t soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* rp, const int32_t* col, const float* xv,
-                         const float* CT, int32_t k, float tau, float grad, const float* lse, float* dS, float* dxv,
-                         int n_cu, hipStream_t s);
+                        float tau, float* lse, double* loss_dev, float* pmax, float* psum, int n_cu, hipStream_t s);
+// rows [c0, c1) whose nonzeros are [p0, p1); dxp: [(p1 - p0) * 8] per-group dX partials
+hipError_t soft_bwd_rows(int64_t c0, int64_t c1, int64_t p0, int64_t p1, const int64_t* rp, const int32_t* col,
+                         const float* xv, const float* CT, int32_t k, float tau, float grad, const float* lse, float* dS,
+                         float* dxp, float* dxv, int n_cu, hipStream_t s);
 hipError_t soft_csc(int64_t N, int64_t d, int64_t nnz, const int64_t* rp, const int32_t* col, const float* xv,
                     int32_t* hist, int64_t* cnt, int64_t* colptr, int64_t* scan_ws, int32_t* xt_row, float* xt_val,
                     hipStream_t s);

@@ -4,15 +4,15 @@
 //             dX_it = sum_j dS_ij C_jt on X's nonzeros (sampled dense-dense product).
 //
 // Layout: C arrives k x d row-major; the kernels gather rows of C^T (d x k,
-// each a contiguous k-vector) per object nonzero.  One workgroup of 256
-// threads owns one object row at a time; each thread holds 16 columns of the
-// row's S in registers (4 float4 groups spaced 1024 apart, so each gather is a
-// fully coalesced 4 KB read), column chunks of 4096 are merged with an online
-// max / sum-exp.  Nothing of size N x k is kept: the backward recomputes S
-// per row and materialises dS only for a chunk of rows, from which dC is
-// accumulated term-major over a CSC copy of X whose lists are in ascending
-// row order, chunk after chunk: a fixed summation order, so results are
-// run-to-run deterministic.
+// each a contiguous k-vector) per object nonzero.  The columns are split into
+// 8 groups, one per XCD (workgroup b takes group b mod 8), so that each XCD's
+// L2 holds its group's slices of the hot terms' rows; a workgroup of 256
+// threads owns one (row, group) at a time.  The forward keeps a per-group max
+// and sum-exp of S / tau and merges the groups in order.  Nothing of size
+// N x k is kept: the backward recomputes S per row and materialises dS only
+// for a chunk of rows, from which dC is accumulated term-major over a CSC copy
+// of X whose lists are in ascending row order, chunk after chunk.  Every sum
+// has a fixed order, so results are run-to-run deterministic.
 #include <algorithm>
 
 #include "internal.h"
@@ -21,9 +21,9 @@
 namespace sivf {
 
 constexpr int kSoftThreads = 256;
-constexpr int kSoftCols = 16;                       // columns per thread per chunk
+constexpr int kSoftCols = 16;                       // dC pass: columns per thread per chunk
 constexpr int kSoftChunk = kSoftThreads * kSoftCols;  // 4096 columns per chunk
-constexpr int kSoftTermsInLds = 256;                // row entries staged per pass
+constexpr int kSoftTermsInLds = 256;                // forward: row entries staged per pass
 constexpr int kDctRows = 4;                         // dS rows in flight per dC step
 
 // ---------------------------------------------------------------- transpose
@@ -78,82 +78,138 @@ __device__ inline float block_sum_f32(float v, float* sh) {
 // Column index of this thread's q-th value (q = 0..15) inside a 4096 chunk.
 __device__ inline int soft_col(int q) { return (q >> 2) * (kSoftThreads * 4) + threadIdx.x * 4 + (q & 3); }
 
-// acc[q] = sum over the row's terms of v * CT[t][ch0 + soft_col(q)] (columns >= k read as 0).
-__device__ inline void soft_row_chunk(const int64_t r0, const int n, const int32_t* __restrict__ col,
-                                      const float* __restrict__ xv, const float* __restrict__ CT, int32_t k,
-                                      int64_t ch0, float acc[kSoftCols], int32_t* s_t, float* s_v) {
-#pragma unroll
-    for (int q = 0; q < kSoftCols; ++q) acc[q] = 0.0f;
-    for (int h0 = 0; h0 < n; h0 += kSoftTermsInLds) {
-        const int m = min(kSoftTermsInLds, n - h0);
-        __syncthreads();
-        for (int h = threadIdx.x; h < m; h += kSoftThreads) {
-            s_t[h] = col[r0 + h0 + h];
-            s_v[h] = xv[r0 + h0 + h];
-        }
-        __syncthreads();
-        const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
-        for (int h = 0; h < m; ++h) {
-            const float v = s_v[h];
-            const float* row = CT + (int64_t)s_t[h] * k + ch0;
-            if (full) {
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const float4 c4 = *reinterpret_cast<const float4*>(row + g * (kSoftThreads * 4) + threadIdx.x * 4);
-                    acc[4 * g + 0] = fmaf(v, c4.x, acc[4 * g + 0]);
-                    acc[4 * g + 1] = fmaf(v, c4.y, acc[4 * g + 1]);
-                    acc[4 * g + 2] = fmaf(v, c4.z, acc[4 * g + 2]);
-                    acc[4 * g + 3] = fmaf(v, c4.w, acc[4 * g + 3]);
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < kSoftCols; ++q) {
-                    const int64_t c = ch0 + soft_col(q);
-                    if (c < k) acc[q] = fmaf(v, row[soft_col(q)], acc[q]);
-                }
-            }
-        }
-    }
+// ---------------------------------------------------------------- forward by column groups
+// Workgroups are dispatched to the 8 XCDs in turn, so workgroup b runs on XCD
+// b mod 8.  Workgroup b takes column group x = b mod 8, columns
+// [x kc, (x + 1) kc) with kc = ceil(k / 8) rounded up to a multiple of 4, for
+// every row it visits: each XCD then gathers only its group's slice of a
+// C^T row (2 KB at k = 4096), so the hot terms' slices stay in its L2.  A
+// workgroup sums S for 512 columns at a time (thread (c4, h): columns
+// 4 c4 .. 4 c4 + 3, the h-th half of the terms in order; the halves are added
+// h = 0 first) and keeps the group's max of S / tau and sum of exp(S / tau -
+// max); k_soft_lse_combine merges the 8 groups of a row in group order.
+constexpr int kSoftGroups = 8;
+constexpr int kFwdCols = 512;   // columns per pass of a workgroup
+
+__host__ __device__ inline int64_t soft_group_width(int64_t k) {
+    return ((k + kSoftGroups - 1) / kSoftGroups + 3) & ~(int64_t)3;
 }
 
-// lse of one row over all k columns (online merge across 4096-column chunks).
-__device__ inline float soft_row_lse(const int64_t r0, const int n, const int32_t* __restrict__ col,
-                                     const float* __restrict__ xv, const float* __restrict__ CT, int32_t k,
-                                     float inv_tau, int32_t* s_t, float* s_v, float* sh) {
-    float m = -INFINITY, z = 0.0f;
-    for (int64_t ch0 = 0; ch0 < k; ch0 += kSoftChunk) {
-        float acc[kSoftCols];
-        soft_row_chunk(r0, n, col, xv, CT, k, ch0, acc, s_t, s_v);
-        float lm = -INFINITY;
-#pragma unroll
-        for (int q = 0; q < kSoftCols; ++q)
-            if (ch0 + soft_col(q) < k) lm = fmaxf(lm, acc[q] * inv_tau);
-        const float cm = block_max_f32(lm, sh);
-        const float nm = fmaxf(m, cm);
-        float ls = 0.0f;
-#pragma unroll
-        for (int q = 0; q < kSoftCols; ++q)
-            if (ch0 + soft_col(q) < k) ls += expf(acc[q] * inv_tau - nm);
-        const float cs = block_sum_f32(ls, sh);
-        z = z * expf(m - nm) + cs;
-        m = nm;
-    }
-    return m + logf(z);
-}
-
-__global__ __launch_bounds__(kSoftThreads) void k_soft_fwd(int64_t N, const int64_t* __restrict__ rp,
-                                                           const int32_t* __restrict__ col, const float* __restrict__ xv,
-                                                           const float* __restrict__ CT, int32_t k, float inv_tau,
-                                                           float* __restrict__ lse) {
+__global__ __launch_bounds__(kSoftThreads) void k_soft_fwd_part(int64_t N, const int64_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ col,
+                                                                const float* __restrict__ xv,
+                                                                const float* __restrict__ CT, int32_t k, float inv_tau,
+                                                                float* __restrict__ pmax, float* __restrict__ psum) {
     __shared__ int32_t s_t[kSoftTermsInLds];
     __shared__ float s_v[kSoftTermsInLds];
+    __shared__ float4 half1[kFwdCols / 4];
     __shared__ float sh[kSoftThreads / 64];
-    for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
+    const int c4 = threadIdx.x % (kFwdCols / 4), h = threadIdx.x / (kFwdCols / 4);
+    const int64_t rstride = gridDim.x / kSoftGroups;
+    for (int64_t i = blockIdx.x / kSoftGroups; i < N; i += rstride) {
         const int64_t r0 = rp[i];
         const int n = (int)(rp[i + 1] - r0);
-        const float l = soft_row_lse(r0, n, col, xv, CT, k, inv_tau, s_t, s_v, sh);
-        if (threadIdx.x == 0) lse[i] = l;
+        float m = -INFINITY, z = 0.0f;
+        for (int64_t cb = g0; cb < g1; cb += kFwdCols) {
+            const int64_t c = cb + 4 * c4;   // this thread's first column
+            const bool vec = (k & 3) == 0 && c + 4 <= g1;
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int h0 = 0; h0 < n; h0 += kSoftTermsInLds) {
+                const int mm = min(kSoftTermsInLds, n - h0);
+                __syncthreads();
+                for (int e = threadIdx.x; e < mm; e += kSoftThreads) {
+                    s_t[e] = col[r0 + h0 + e];
+                    s_v[e] = xv[r0 + h0 + e];
+                }
+                __syncthreads();
+                const int half = (mm + 1) / 2;
+                const int lo = h == 0 ? 0 : half, hi = h == 0 ? half : mm;
+                if (vec) {
+                    // four terms' slices in flight, then their products in term order
+                    for (int e0 = lo; e0 < hi; e0 += 4) {
+                        float4 g[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = min(e0 + u, hi - 1);
+                            g[u] = *reinterpret_cast<const float4*>(CT + (int64_t)s_t[e] * k + c);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (e0 + u < hi) {
+                                const float v = s_v[e0 + u];
+                                acc.x = fmaf(v, g[u].x, acc.x);
+                                acc.y = fmaf(v, g[u].y, acc.y);
+                                acc.z = fmaf(v, g[u].z, acc.z);
+                                acc.w = fmaf(v, g[u].w, acc.w);
+                            }
+                        }
+                    }
+                } else if (c < g1) {
+                    for (int e = lo; e < hi; ++e) {
+                        const float v = s_v[e];
+                        const float* row = CT + (int64_t)s_t[e] * k + c;
+                        acc.x = fmaf(v, row[0], acc.x);
+                        if (c + 1 < g1) acc.y = fmaf(v, row[1], acc.y);
+                        if (c + 2 < g1) acc.z = fmaf(v, row[2], acc.z);
+                        if (c + 3 < g1) acc.w = fmaf(v, row[3], acc.w);
+                    }
+                }
+            }
+            // S = first half + second half
+            __syncthreads();
+            if (h == 1) half1[c4] = acc;
+            __syncthreads();
+            float lm = -INFINITY;
+            if (h == 0) {
+                const float4 o = half1[c4];
+                acc.x = acc.x + o.x;
+                acc.y = acc.y + o.y;
+                acc.z = acc.z + o.z;
+                acc.w = acc.w + o.w;
+                if (c + 0 < g1) lm = fmaxf(lm, acc.x * inv_tau);
+                if (c + 1 < g1) lm = fmaxf(lm, acc.y * inv_tau);
+                if (c + 2 < g1) lm = fmaxf(lm, acc.z * inv_tau);
+                if (c + 3 < g1) lm = fmaxf(lm, acc.w * inv_tau);
+            }
+            const float cm = block_max_f32(lm, sh);
+            const float nm = fmaxf(m, cm);
+            float ls = 0.0f;
+            if (h == 0) {
+                if (c + 0 < g1) ls += expf(acc.x * inv_tau - nm);
+                if (c + 1 < g1) ls += expf(acc.y * inv_tau - nm);
+                if (c + 2 < g1) ls += expf(acc.z * inv_tau - nm);
+                if (c + 3 < g1) ls += expf(acc.w * inv_tau - nm);
+            }
+            const float cs = block_sum_f32(ls, sh);
+            z = z * expf(m - nm) + cs;
+            m = nm;
+        }
+        if (threadIdx.x == 0) {
+            pmax[i * kSoftGroups + x] = m;
+            psum[i * kSoftGroups + x] = z;
+        }
     }
+}
+
+// lse_i = M + log sum_x psum_x exp(pmax_x - M), M = max_x pmax_x, groups in order
+// (a group without columns has pmax = -inf, psum = 0)
+__global__ void k_soft_lse_combine(int64_t N, const float* __restrict__ pmax, const float* __restrict__ psum,
+                                   float* __restrict__ lse) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float M = -INFINITY;
+#pragma unroll
+    for (int x = 0; x < kSoftGroups; ++x) M = fmaxf(M, pmax[i * kSoftGroups + x]);
+    float z = 0.0f;
+#pragma unroll
+    for (int x = 0; x < kSoftGroups; ++x) {
+        const float px = pmax[i * kSoftGroups + x];
+        if (px > -INFINITY) z += psum[i * kSoftGroups + x] * expf(px - M);
+    }
+    lse[i] = M + logf(z);
 }
 
 // loss = -sum_i lse_i in FP64: each thread sums a contiguous range in order,
@@ -174,11 +230,14 @@ __global__ __launch_bounds__(1024) void k_soft_loss(const float* __restrict__ ls
 }
 
 hipError_t soft_forward(int64_t N, const int64_t* rp, const int32_t* col, const float* xv, const float* CT, int32_t k,
-                        float tau, float* lse, double* loss_dev, int n_cu, hipStream_t s) {
-    int64_t grid = std::min<int64_t>(N, (int64_t)n_cu * 8);
-    if (grid > 0)
-        hipLaunchKernelGGL(k_soft_fwd, dim3((unsigned)grid), dim3(kSoftThreads), 0, s, N, rp, col, xv, CT, k, 1.0f / tau,
-                           lse);
+                        float tau, float* lse, double* loss_dev, float* pmax, float* psum, int n_cu, hipStream_t s) {
+    if (N > 0) {
+        // a multiple of the group count, so every workgroup keeps its group
+        const int64_t per_group = std::min<int64_t>(N, (int64_t)n_cu * 8 / kSoftGroups);
+        hipLaunchKernelGGL(k_soft_fwd_part, dim3((unsigned)(per_group * kSoftGroups)), dim3(kSoftThreads), 0, s, N, rp,
+                           col, xv, CT, k, 1.0f / tau, pmax, psum);
+        hipLaunchKernelGGL(k_soft_lse_combine, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, pmax, psum, lse);
+    }
     hipLaunchKernelGGL(k_soft_loss, dim3(1), dim3(1024), 0, s, lse, N, loss_dev);
     return hipGetLastError();
 }
@@ -187,15 +246,17 @@ hipError_t soft_forward(int64_t N, const int64_t* rp, const int32_t* col, const 
 // For rows [c0, c1): recompute S, write dS (row-major, k columns) and dX on the
 // row's nonzeros, reading each gathered C^T value once.
 //
-// A workgroup owns a row and walks its columns in blocks of W.  For a block it
-// stages the row's C^T slices (W floats per term, kBwTerms terms per batch) in
-// LDS, then
+// Workgroup b takes column group b mod 8 (the forward's groups: one per XCD)
+// of each row it visits and walks the group's columns in blocks of W.  For a
+// block it stages the row's C^T slices (W floats per term, kBwTerms terms per
+// batch) in LDS, then
 //   S:  thread (c, h) sums the h-th of 256 / W contiguous ranges of the terms
 //       for column c (in term order), and the ranges' sums are added in order;
 //   dS: -g exp(S / tau - lse) / tau, written out and kept in LDS;
 //   dX: thread j dots dS with term j's slice (columns in order, four
 //       interleaved partial sums added in a fixed order) and adds the block's
-//       dot to its running dX_j, blocks in column order.
+//       dot to its running dX_j, blocks in column order; the group's dX_j goes
+//       to a partial array, and k_soft_dx_combine adds the 8 groups in order.
 // Rows with more than kBwTerms terms stage their terms batch by batch and
 // gather each batch a second time for dX.  Rows are W + 4 floats apart, so a
 // term's slice and dS are read 16 bytes at a time in the dX pass; the S pass
@@ -238,11 +299,11 @@ __device__ inline void bw_stage_terms(BwLds<W>& sh, const int32_t* __restrict__ 
 // The 16-byte path and the element path are separate loops, so the former
 // stays one 16-byte load per slot.
 template <int W>
-__device__ inline void bw_gather(const BwLds<W>& sh, const float* __restrict__ CT, int32_t k, int64_t cb, int m,
-                                 int e0, float4 (&g)[kBwPre]) {
+__device__ inline void bw_gather(const BwLds<W>& sh, const float* __restrict__ CT, int32_t k, int64_t cb, int64_t lim,
+                                 int m, int e0, float4 (&g)[kBwPre]) {
     constexpr int per = W / 4;
     const int tot = m * per;
-    if ((k & 3) == 0 && cb + W <= k) {
+    if ((k & 3) == 0 && cb + W <= lim) {
         // the slots' term ids first (one LDS wait), then the loads
         int32_t tt[kBwPre];
 #pragma unroll
@@ -263,10 +324,10 @@ __device__ inline void bw_gather(const BwLds<W>& sh, const float* __restrict__ C
             if (e < tot) {
                 const float* src = CT + (int64_t)sh.t[e / per] * k + cb + 4 * (e % per);
                 const int64_t c = cb + 4 * (e % per);
-                g[u].x = c + 0 < k ? src[0] : 0.0f;
-                g[u].y = c + 1 < k ? src[1] : 0.0f;
-                g[u].z = c + 2 < k ? src[2] : 0.0f;
-                g[u].w = c + 3 < k ? src[3] : 0.0f;
+                g[u].x = c + 0 < lim ? src[0] : 0.0f;
+                g[u].y = c + 1 < lim ? src[1] : 0.0f;
+                g[u].z = c + 2 < lim ? src[2] : 0.0f;
+                g[u].w = c + 3 < lim ? src[3] : 0.0f;
             }
         }
     }
@@ -283,13 +344,14 @@ __device__ inline void bw_put(BwLds<W>& sh, int m, int e0, const float4 (&g)[kBw
     }
 }
 
-// L[e][c] = C^T[t_e][cb + c] for e < m, c < W (columns >= k read as 0)
+// L[e][c] = C^T[t_e][cb + c] for e < m, c < W (columns >= lim read as 0)
 template <int W>
-__device__ inline void bw_stage_slices(BwLds<W>& sh, const float* __restrict__ CT, int32_t k, int64_t cb, int m) {
+__device__ inline void bw_stage_slices(BwLds<W>& sh, const float* __restrict__ CT, int32_t k, int64_t cb, int64_t lim,
+                                       int m) {
     const int tot = m * (W / 4);
     for (int e0 = 0; e0 < tot; e0 += kBwPre * kSoftThreads) {
         float4 g[kBwPre];
-        bw_gather<W>(sh, CT, k, cb, m, e0, g);
+        bw_gather<W>(sh, CT, k, cb, lim, m, e0, g);
         bw_put<W>(sh, m, e0, g);
     }
 }
@@ -347,20 +409,25 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
                                                                 const float* __restrict__ xv,
                                                                 const float* __restrict__ CT, int32_t k, float inv_tau,
                                                                 float neg_g_over_tau, const float* __restrict__ lse,
-                                                                float* __restrict__ dS, float* __restrict__ dxv) {
+                                                                float* __restrict__ dS, float* __restrict__ dxp) {
     __shared__ BwLds<W> sh;
     const int c = threadIdx.x % W, h = threadIdx.x / W;
-    for (int64_t i = c0 + blockIdx.x; i < c1; i += gridDim.x) {
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
+    const int64_t pbase = rp[c0];
+    for (int64_t i = c0 + blockIdx.x / kSoftGroups; i < c1; i += gridDim.x / kSoftGroups) {
         const int64_t r0 = rp[i];
         const int n = (int)(rp[i + 1] - r0);
         const int nb = (n + kBwTerms - 1) / kBwTerms;
         const float l = lse[i];
         float* dsrow = dS + (i - c0) * (int64_t)k;
+        float* dxrow = dxp + (r0 - pbase) * kSoftGroups + x;   // entry e at dxrow[e * 8]
         bw_bar();
         if (nb == 1) bw_stage_terms<W>(sh, col, xv, r0, 0, n);
-        float dxr = 0.0f;   // dX of term threadIdx.x (one batch only)
-        for (int64_t cb = 0; cb < k; cb += W) {
-            const int w = (int)min((int64_t)W, k - cb);
+        float dxr = 0.0f;   // dX of term threadIdx.x in this group (one batch only)
+        for (int64_t cb = g0; cb < g1; cb += W) {
+            const int w = (int)min((int64_t)W, g1 - cb);
             float s = 0.0f;
             for (int b = 0; b < nb; ++b) {
                 const int t0 = b * kBwTerms, m = min(kBwTerms, n - t0);
@@ -369,7 +436,7 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
                     bw_stage_terms<W>(sh, col, xv, r0, t0, m);
                     bw_bar();
                 }
-                bw_stage_slices<W>(sh, CT, k, cb, m);
+                bw_stage_slices<W>(sh, CT, k, cb, g1, m);
                 bw_bar();
                 s += bw_s_partial<W>(sh, m, c, h);
             }
@@ -382,29 +449,47 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
                     bw_bar();
                     bw_stage_terms<W>(sh, col, xv, r0, t0, m);
                     bw_bar();
-                    bw_stage_slices<W>(sh, CT, k, cb, m);
+                    bw_stage_slices<W>(sh, CT, k, cb, g1, m);
                     bw_bar();
                     if (threadIdx.x < m) {
-                        const int64_t p = r0 + t0 + threadIdx.x;
-                        dxv[p] = (cb == 0 ? 0.0f : dxv[p]) + bw_dot<W>(sh, threadIdx.x, w);
+                        float* q = dxrow + (int64_t)(t0 + threadIdx.x) * kSoftGroups;
+                        *q = (cb == g0 ? 0.0f : *q) + bw_dot<W>(sh, threadIdx.x, w);
                     }
                 }
             }
         }
-        if (nb == 1 && threadIdx.x < n) dxv[r0 + threadIdx.x] = dxr;
+        if (nb == 1) {
+            if (threadIdx.x < n) dxrow[(int64_t)threadIdx.x * kSoftGroups] = dxr;
+        } else if (g0 >= g1) {
+            for (int e = threadIdx.x; e < n; e += kSoftThreads) dxrow[(int64_t)e * kSoftGroups] = 0.0f;
+        }
     }
+}
+
+// dxv[p] = sum over the 8 column groups, in group order, of dxp[(p - p0) * 8 + x]
+__global__ void k_soft_dx_combine(int64_t p0, int64_t p1, const float* __restrict__ dxp, float* __restrict__ dxv) {
+    const int64_t p = p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= p1) return;
+    const float* q = dxp + (p - p0) * kSoftGroups;
+    float a = q[0];
+#pragma unroll
+    for (int x = 1; x < kSoftGroups; ++x) a = a + q[x];
+    dxv[p] = a;
 }
 
 constexpr int kBwW = 64;   // columns per block of the rows pass
 
-hipError_t soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* rp, const int32_t* col, const float* xv,
-                         const float* CT, int32_t k, float tau, float grad, const float* lse, float* dS, float* dxv,
-                         int n_cu, hipStream_t s) {
-    const int per_cu = (int)(160 * 1024 / sizeof(BwLds<kBwW>));
-    int64_t grid = std::min<int64_t>(c1 - c0, (int64_t)n_cu * std::max(per_cu, 1));
-    if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_soft_bwd_rows<kBwW>), dim3((unsigned)grid), dim3(kSoftThreads), 0, s, c0, c1,
-                       rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxv);
+hipError_t soft_bwd_rows(int64_t c0, int64_t c1, int64_t p0, int64_t p1, const int64_t* rp, const int32_t* col,
+                         const float* xv, const float* CT, int32_t k, float tau, float grad, const float* lse, float* dS,
+                         float* dxp, float* dxv, int n_cu, hipStream_t s) {
+    if (c1 <= c0) return hipSuccess;
+    const int per_cu = std::max(1, (int)(160 * 1024 / sizeof(BwLds<kBwW>)));
+    const int64_t per_group = std::min<int64_t>(c1 - c0, (int64_t)n_cu * per_cu / kSoftGroups);
+    hipLaunchKernelGGL((k_soft_bwd_rows<kBwW>), dim3((unsigned)(per_group * kSoftGroups)), dim3(kSoftThreads), 0, s, c0,
+                       c1, rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxp);
+    if (p1 > p0)
+        hipLaunchKernelGGL(k_soft_dx_combine, dim3((unsigned)((p1 - p0 + 255) / 256)), dim3(256), 0, s, p0, p1, dxp,
+                           dxv);
     return hipGetLastError();
 }
 
