@@ -20,7 +20,7 @@ PROBE_LIB = os.path.join(HERE, "libsivf_probe.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["k_util.hip", "k_ivf.hip", "k_assign.hip", "k_update.hip", "k_soft.hip", "api.cpp"]
-HEADERS = ["internal.h", "wave.h"]
+HEADERS = ["internal.h", "soft.h", "wave.h"]
 ARCH = os.environ.get("SIVF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "soft.h"
 
 using namespace sivf;
 

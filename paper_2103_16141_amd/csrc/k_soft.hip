@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "soft.h"
 #include "wave.h"
 
 namespace sivf {

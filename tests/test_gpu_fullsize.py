@@ -11,9 +11,10 @@ N = 8M objects, D = 140k, k = 10k, automatic tiles (the headline workload):
   * past the iterations the file holds, one step at a time against the
     oracle at iteration 4 and at the late, ICP-heavy iteration 20: the
     oracle's update of the GPU's previous assignment gives the GPU's
-    centroids bit for bit, >= 200,000 sampled objects (>= 50,000 of them in
-    the ICP branch at iteration 20) match the oracle's unfiltered argmax,
-    flags, moved and the exact mult-add count over all objects;
+    centroids bit for bit, then 200,000 sampled objects (iteration 4) or all
+    8M objects (iteration 20, 1.66M of them in the ICP branch) match the
+    oracle's unfiltered argmax, and flags, moved and the exact mult-add count
+    are checked over all objects;
   * the exact FP64 objective never decreases;
   * the structured file after update 2 against the oracle's; sampled
     centroids after update 1 against dense FP64 numpy means (not the oracle);
@@ -94,19 +95,34 @@ def _check_golden_step(r, it, st, a, lam, what=""):
 
 def _one_step(corpus, cents, r, a_prev, lam_prev, a, lam, st, rng, n_sample, n_icp_min=0):
     """Assignment step r against the oracle from the GPU's centroids mu^[r-1]
-    (verified against the oracle beforehand): sampled objects against the
-    oracle's unfiltered argmax, flags, moved and the mult-add count over all."""
+    (verified against the oracle beforehand): sampled objects (all of them if
+    n_sample is None) against the oracle's unfiltered argmax, flags, moved and
+    the mult-add count over all."""
     k = cents.k
     icp = np.nonzero(lam_prev[a_prev] == 1)[0]
-    uni = rng.choice(corpus.n, n_sample, replace=False)
-    extra = rng.choice(icp, min(len(icp), n_icp_min), replace=False) if n_icp_min else np.zeros(0, np.int64)
-    sample = np.unique(np.concatenate([uni, extra]))
-    n_icp = int(np.isin(sample, icp).sum())
-    log("iteration %d: oracle on %d sampled objects (%d in the ICP branch)" % (r, len(sample), n_icp))
+    if n_sample is None:
+        sample = None
+        n_icp = len(icp)
+        log("iteration %d: oracle on all %d objects (%d in the ICP branch)" % (r, corpus.n, n_icp))
+    else:
+        uni = rng.choice(corpus.n, n_sample, replace=False)
+        extra = rng.choice(icp, min(len(icp), n_icp_min), replace=False) if n_icp_min else np.zeros(0, np.int64)
+        sample = np.unique(np.concatenate([uni, extra]))
+        n_icp = int(np.isin(sample, icp).sum())
+        log("iteration %d: oracle on %d sampled objects (%d in the ICP branch)" % (r, len(sample), n_icp))
     assert n_icp >= n_icp_min
-    ref, ref_own, _ = oracle.assign(corpus, cents, rows=sample)
-    bad = np.nonzero(a[sample] != ref)[0]
-    assert len(bad) == 0, "iteration %d: %d sampled objects differ, e.g. %s" % (r, len(bad), sample[bad][:5])
+    if sample is None:
+        # all objects, a million at a time (progress in the log)
+        for lo in range(0, corpus.n, 1_000_000):
+            rows = np.arange(lo, min(corpus.n, lo + 1_000_000))
+            ref, _, _ = oracle.assign(corpus, cents, rows=rows)
+            bad = np.nonzero(a[rows] != ref)[0]
+            assert len(bad) == 0, "iteration %d: %d objects differ, e.g. %s" % (r, len(bad), rows[bad][:5])
+            log("  objects %d..%d match" % (lo, rows[-1]))
+    else:
+        ref, _, _ = oracle.assign(corpus, cents, rows=sample)
+        bad = np.nonzero(a[sample] != ref)[0]
+        assert len(bad) == 0, "iteration %d: %d sampled objects differ, e.g. %s" % (r, len(bad), sample[bad][:5])
     lam_ref, moved = oracle.mark_invariant(a_prev, a, k, first=False)
     assert np.array_equal(lam, lam_ref), "iteration %d: flags differ" % r
     assert st["moved"] == moved
@@ -117,7 +133,8 @@ def _one_step(corpus, cents, r, a_prev, lam_prev, a, lam, st, rng, n_sample, n_i
 
 def test_headline_trajectory(headline):
     """Iterations 1..20 of the headline workload: full-N digests where the
-    oracle's run reaches, one-step sampled checks at 4 and 20 beyond it."""
+    oracle's run reaches, one-step checks beyond it at 4 (sampled) and 20
+    (every object)."""
     from paper_2103_16141_amd.api import Context, Lloyd
     corpus, ids, w, X = headline
     k, d = w["k"], corpus.d
@@ -143,7 +160,9 @@ def test_headline_trajectory(headline):
             assert abs(st["objective"] - ref) <= 1e-12 * abs(ref), (r, st["objective"], ref)
         elif r in need:
             assert cents is not None
-            _one_step(corpus, cents, r, a_prev, lam_prev, a, lam, st, rng, 200_000, 50_000 if r == last else 0)
+            # iteration 20: every object; iteration 4: a uniform sample
+            _one_step(corpus, cents, r, a_prev, lam_prev, a, lam, st, rng, None if r == last else 200_000,
+                      1_000_000 if r == last else 0)
         if r >= 2:
             assert objective[-1] >= objective[-2] - 1e-12 * abs(objective[-2]), "objective fell at %d" % r
         if r == last:
