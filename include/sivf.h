@@ -107,7 +107,9 @@ typedef struct {
                                    (diagnostics only; not exact) */
     size_t workspace_cap_bytes; /* 0 = unlimited; else device bytes the ctx and its
                                    files may hold; exceeding it gives SIVF_E_NOMEM */
-    float head_density;         /* in [0, 1]; default 0.5.  Terms held by at least this
+    float head_density;         /* in [0, 1], or negative (the default, -1) for the
+                                   precision's own value: 0.5 with SIVF_F32 postings, 0.3
+                                   with SIVF_BF16.  Terms held by at least this
                                    fraction of the k centroids also get a dense row of
                                    posting values (zeros for absent centroids) that the
                                    walk reads instead of the term's lists (objects in

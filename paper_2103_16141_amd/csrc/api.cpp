@@ -752,7 +752,7 @@ sivf_status sivf_default_options(sivf_options* opt) {
     opt->k_tile = 0;
     opt->certify = 1;
     opt->workspace_cap_bytes = 0;
-    opt->head_density = 0.5f;
+    opt->head_density = -1.0f;
     opt->tiles_per_launch = 0;
     opt->exact_objective = 0;
     return SIVF_OK;
@@ -767,7 +767,10 @@ sivf_status sivf_create(sivf_ctx** out, int device, void* hip_stream, const sivf
     if (o.posting_dtype != SIVF_F32 && o.posting_dtype != SIVF_BF16) return SIVF_E_INVALID;
     if (o.filter_mode < 0 || o.filter_mode > 3) return SIVF_E_INVALID;
     if (o.k_tile != 0 && (o.k_tile < 64 || o.k_tile > kMaxTile || o.k_tile % 64 != 0)) return SIVF_E_INVALID;
-    if (!(o.head_density >= 0.0f && o.head_density <= 1.0f)) return SIVF_E_INVALID;
+    if (!(o.head_density <= 1.0f)) return SIVF_E_INVALID;   // NaN fails too
+    // negative: the precision's own density (dense rows cost half the bytes
+    // in BF16, so more terms pay for one there)
+    if (o.head_density < 0.0f) o.head_density = o.posting_dtype == SIVF_BF16 ? 0.3f : 0.5f;
     if (o.tiles_per_launch < 0) return SIVF_E_INVALID;
     if (o.exact_objective != 0 && o.exact_objective != 1) return SIVF_E_INVALID;
     int ndev = 0;

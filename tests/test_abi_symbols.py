@@ -42,7 +42,7 @@ def test_default_options_without_gpu():
     opt = N.sivf_options()
     assert lib.sivf_default_options(ctypes.byref(opt)) == 0
     assert opt.posting_dtype == N.SIVF_F32 and opt.certify == 1 and opt.filter_mode == N.SIVF_MODE_SIVF
-    assert opt.k_tile == 0 and opt.workspace_cap_bytes == 0 and opt.head_density == 0.5
+    assert opt.k_tile == 0 and opt.workspace_cap_bytes == 0 and opt.head_density == -1.0
     assert opt.tiles_per_launch == 0
     assert lib.sivf_default_options(None) == -1
 
