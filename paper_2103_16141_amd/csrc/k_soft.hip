@@ -404,6 +404,14 @@ __device__ inline void bw_ds(BwLds<W>& sh, float s, int c, int h, int w, float i
     bw_bar();
 }
 
+// A row whose slices of one block fit one gather round (at most
+// kBwPre * 256 / (W / 4) terms: 128 for W = 64, nearly every row of a
+// Poisson(100) corpus) goes to k_soft_bwd_rows_pf.
+template <int W>
+__device__ inline bool bw_short_row(int n) {
+    return n * (W / 4) <= kBwPre * kSoftThreads;
+}
+
 template <int W>
 __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* __restrict__ rp,
                                                                 const int32_t* __restrict__ col,
@@ -420,6 +428,7 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
     for (int64_t i = c0 + blockIdx.x / kSoftGroups; i < c1; i += gridDim.x / kSoftGroups) {
         const int64_t r0 = rp[i];
         const int n = (int)(rp[i + 1] - r0);
+        if (bw_short_row<W>(n)) continue;   // k_soft_bwd_rows_pf takes it
         const int nb = (n + kBwTerms - 1) / kBwTerms;
         const float l = lse[i];
         float* dsrow = dS + (i - c0) * (int64_t)k;
@@ -467,6 +476,50 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
     }
 }
 
+// The short rows: the same sums in the same order as k_soft_bwd_rows, with
+// the next block's gathers issued before this block's S, dS and dX, waiting
+// in registers (one round of kBwPre float4 per thread) while the block's LDS
+// work runs, so that each block's gather round trip overlaps the previous
+// block.  A kernel of its own: with the long-row path beside it the register
+// allocation would not fit four waves per SIMD.
+template <int W>
+__global__ __launch_bounds__(kSoftThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_soft_bwd_rows_pf(
+    int64_t c0, int64_t c1, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const float* __restrict__ xv, const float* __restrict__ CT, int32_t k, float inv_tau, float neg_g_over_tau,
+    const float* __restrict__ lse, float* __restrict__ dS, float* __restrict__ dxp) {
+    __shared__ BwLds<W> sh;
+    const int c = threadIdx.x % W, h = threadIdx.x / W;
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
+    const int64_t pbase = rp[c0];
+    for (int64_t i = c0 + blockIdx.x / kSoftGroups; i < c1; i += gridDim.x / kSoftGroups) {
+        const int64_t r0 = rp[i];
+        const int n = (int)(rp[i + 1] - r0);
+        if (!bw_short_row<W>(n)) continue;
+        const float l = lse[i];
+        float* dsrow = dS + (i - c0) * (int64_t)k;
+        float* dxrow = dxp + (r0 - pbase) * kSoftGroups + x;   // entry e at dxrow[e * 8]
+        bw_bar();
+        bw_stage_terms<W>(sh, col, xv, r0, 0, n);
+        bw_bar();
+        float4 g[kBwPre];
+        if (g0 < g1) bw_gather<W>(sh, CT, k, g0, g1, n, 0, g);
+        float dxr = 0.0f;
+        for (int64_t cb = g0; cb < g1; cb += W) {
+            const int w = (int)min((int64_t)W, g1 - cb);
+            bw_bar();   // the previous block's readers of L are done
+            bw_put<W>(sh, n, 0, g);
+            if (cb + W < g1) bw_gather<W>(sh, CT, k, cb + W, g1, n, 0, g);
+            bw_bar();
+            const float s = bw_s_partial<W>(sh, n, c, h);
+            bw_ds<W>(sh, s, c, h, w, inv_tau, neg_g_over_tau, l, dsrow, cb);
+            if (threadIdx.x < n) dxr += bw_dot<W>(sh, threadIdx.x, w);
+        }
+        if (threadIdx.x < n) dxrow[(int64_t)threadIdx.x * kSoftGroups] = dxr;
+    }
+}
+
 // dxv[p] = sum over the 8 column groups, in group order, of dxp[(p - p0) * 8 + x]
 __global__ void k_soft_dx_combine(int64_t p0, int64_t p1, const float* __restrict__ dxp, float* __restrict__ dxv) {
     const int64_t p = p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -486,6 +539,9 @@ hipError_t soft_bwd_rows(int64_t c0, int64_t c1, int64_t p0, int64_t p1, const i
     if (c1 <= c0) return hipSuccess;
     const int per_cu = std::max(1, (int)(160 * 1024 / sizeof(BwLds<kBwW>)));
     const int64_t per_group = std::min<int64_t>(c1 - c0, (int64_t)n_cu * per_cu / kSoftGroups);
+    // short rows, then the rest (each kernel skips the other's rows)
+    hipLaunchKernelGGL((k_soft_bwd_rows_pf<kBwW>), dim3((unsigned)(per_group * kSoftGroups)), dim3(kSoftThreads), 0, s,
+                       c0, c1, rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxp);
     hipLaunchKernelGGL((k_soft_bwd_rows<kBwW>), dim3((unsigned)(per_group * kSoftGroups)), dim3(kSoftThreads), 0, s, c0,
                        c1, rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxp);
     if (p1 > p0)
