@@ -404,13 +404,15 @@ __device__ inline void bw_ds(BwLds<W>& sh, float s, int c, int h, int w, float i
     bw_bar();
 }
 
-// A row whose slices of one block fit one gather round (at most
-// kBwPre * 256 / (W / 4) terms: 128 for W = 64, nearly every row of a
-// Poisson(100) corpus) goes to k_soft_bwd_rows_pf.
-template <int W>
-__device__ inline bool bw_short_row(int n) {
-    return n * (W / 4) <= kBwPre * kSoftThreads;
-}
+// Rows of at most kRegTerms terms (nearly every row of a Poisson(100) corpus)
+// go to k_soft_bwd_rows_reg: kRegQ lanes per term slice (4 kRegQ columns per
+// block), kRegU register rounds of 256 / kRegQ terms.  Measured at the full
+// shape: slices of 8 or 4 lanes (6 and 8 waves per SIMD) are slower, the
+// extra shuffle steps and barriers outweighing the occupancy.
+constexpr int kRegQ = 16, kRegU = 8;
+constexpr int kRegTerms = kRegU * (kSoftThreads / kRegQ);
+
+__device__ inline bool bw_short_row(int n) { return n <= kRegTerms; }
 
 template <int W>
 __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int64_t c1, const int64_t* __restrict__ rp,
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
     for (int64_t i = c0 + blockIdx.x / kSoftGroups; i < c1; i += gridDim.x / kSoftGroups) {
         const int64_t r0 = rp[i];
         const int n = (int)(rp[i + 1] - r0);
-        if (bw_short_row<W>(n)) continue;   // k_soft_bwd_rows_pf takes it
+        if (bw_short_row(n)) continue;   // k_soft_bwd_rows_reg takes it
         const int nb = (n + kBwTerms - 1) / kBwTerms;
         const float l = lse[i];
         float* dsrow = dS + (i - c0) * (int64_t)k;
@@ -476,47 +478,153 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows(int64_t c0, int6
     }
 }
 
-// The short rows: the same sums in the same order as k_soft_bwd_rows, with
-// the next block's gathers issued before this block's S, dS and dX, waiting
-// in registers (one round of kBwPre float4 per thread) while the block's LDS
-// work runs, so that each block's gather round trip overlaps the previous
-// block.  A kernel of its own: with the long-row path beside it the register
-// allocation would not fit four waves per SIMD.
-template <int W>
-__global__ __launch_bounds__(kSoftThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_soft_bwd_rows_pf(
-    int64_t c0, int64_t c1, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-    const float* __restrict__ xv, const float* __restrict__ CT, int32_t k, float inv_tau, float neg_g_over_tau,
-    const float* __restrict__ lse, float* __restrict__ dS, float* __restrict__ dxp) {
-    __shared__ BwLds<W> sh;
-    const int c = threadIdx.x % W, h = threadIdx.x / W;
+// The short rows (bw_short_row), without staging the slices in LDS.  For a
+// block of 4Q columns, thread (wave v, lane l) holds in registers, for
+// u = 0 .. U-1, the four columns 4q .. 4q+3 (q = l mod Q) of term
+// u * (256 / Q) + (64 / Q) v + l / Q of the row: a term's slice lies in Q
+// consecutive lanes.  Then
+//   S:  each thread sums its terms' products in u order; the 64 / Q lane
+//       groups of a wave are added by xor shuffles (distance Q, 2Q, ..., 32),
+//       the four waves' sums through LDS in wave order;
+//   dS: as in k_soft_bwd_rows, from 4Q threads;
+//   dX: each thread dots dS with its slot (4 columns in order), the 16 lanes
+//       of the term (one DPP row) are added by row rotations (8, 4, 2, 1;
+//       through LDS shuffles instead this pass takes 11% longer), and the
+//       block's sum goes to the term's running dX, blocks in column order.
+// Every lane of such a tree ends with the same value (each step adds two
+// partners' values, and addition commutes), and every step has a fixed
+// association, so the result is run-to-run identical.  Each gathered value is
+// read from memory once and used twice from registers.
+template <int Q, int U>
+struct RegLds {
+    static constexpr int kTerms = U * (kSoftThreads / Q);
+    int32_t t[kTerms];
+    float v[kTerms];
+    alignas(16) float4 P[2][kSoftThreads / 64][Q];
+    alignas(16) float D[2][4 * Q];
+};
+
+// sum over the 16 lanes of this lane's DPP row (row_ror 8, 4, 2, 1)
+__device__ inline float row16_sum(float p) {
+    p = p + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0x128, 0xf, 0xf, false));
+    p = p + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0x124, 0xf, 0xf, false));
+    p = p + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0x122, 0xf, 0xf, false));
+    p = p + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(p), 0x121, 0xf, 0xf, false));
+    return p;
+}
+
+__device__ inline float4 add4(float4 a, float4 b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
+__device__ inline float4 shfl_xor4(float4 a, int o) {
+    return make_float4(__shfl_xor(a.x, o, 64), __shfl_xor(a.y, o, 64), __shfl_xor(a.z, o, 64), __shfl_xor(a.w, o, 64));
+}
+
+template <int Q, int U>
+__global__ __launch_bounds__(kSoftThreads) void k_soft_bwd_rows_reg(int64_t c0, int64_t c1,
+                                                                    const int64_t* __restrict__ rp,
+                                                                    const int32_t* __restrict__ col,
+                                                                    const float* __restrict__ xv,
+                                                                    const float* __restrict__ CT, int32_t k,
+                                                                    float inv_tau, float neg_g_over_tau,
+                                                                    const float* __restrict__ lse,
+                                                                    float* __restrict__ dS, float* __restrict__ dxp) {
+    static_assert(Q == 16, "a term's slice is one DPP row");
+    constexpr int kTpr = kSoftThreads / Q;   // terms per register round
+    constexpr int kCols = 4 * Q;             // columns per block
+    __shared__ RegLds<Q, U> sh;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane % Q, sub = lane / Q;
     const int x = blockIdx.x % kSoftGroups;
     const int64_t kc = soft_group_width(k);
     const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
     const int64_t pbase = rp[c0];
+    int par = 0;
     for (int64_t i = c0 + blockIdx.x / kSoftGroups; i < c1; i += gridDim.x / kSoftGroups) {
         const int64_t r0 = rp[i];
         const int n = (int)(rp[i + 1] - r0);
-        if (!bw_short_row<W>(n)) continue;
+        if (n > RegLds<Q, U>::kTerms) continue;   // k_soft_bwd_rows takes it
         const float l = lse[i];
         float* dsrow = dS + (i - c0) * (int64_t)k;
         float* dxrow = dxp + (r0 - pbase) * kSoftGroups + x;   // entry e at dxrow[e * 8]
-        bw_bar();
-        bw_stage_terms<W>(sh, col, xv, r0, 0, n);
-        bw_bar();
-        float4 g[kBwPre];
-        if (g0 < g1) bw_gather<W>(sh, CT, k, g0, g1, n, 0, g);
-        float dxr = 0.0f;
-        for (int64_t cb = g0; cb < g1; cb += W) {
-            const int w = (int)min((int64_t)W, g1 - cb);
-            bw_bar();   // the previous block's readers of L are done
-            bw_put<W>(sh, n, 0, g);
-            if (cb + W < g1) bw_gather<W>(sh, CT, k, cb + W, g1, n, 0, g);
-            bw_bar();
-            const float s = bw_s_partial<W>(sh, n, c, h);
-            bw_ds<W>(sh, s, c, h, w, inv_tau, neg_g_over_tau, l, dsrow, cb);
-            if (threadIdx.x < n) dxr += bw_dot<W>(sh, threadIdx.x, w);
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += kSoftThreads) {
+            sh.t[e] = col[r0 + e];
+            sh.v[e] = xv[r0 + e];
         }
-        if (threadIdx.x < n) dxrow[(int64_t)threadIdx.x * kSoftGroups] = dxr;
+        __syncthreads();
+        float xu[U], dxr[U];
+        int32_t tu[U];   // term id, -1 past the row's end
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = u * kTpr + (64 / Q) * wv + sub;
+            xu[u] = e < n ? sh.v[e] : 0.0f;
+            tu[u] = e < n ? sh.t[e] : -1;
+            dxr[u] = 0.0f;
+        }
+        for (int64_t cb = g0; cb < g1; cb += kCols) {
+            const int w = (int)min((int64_t)kCols, g1 - cb);
+            const int64_t cq = cb + 4 * q;   // this lane's first column
+            float4 g[U];
+            if ((k & 3) == 0 && cq + 4 <= g1) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    g[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (tu[u] >= 0) g[u] = *reinterpret_cast<const float4*>(CT + (int64_t)tu[u] * k + cq);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    g[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (tu[u] >= 0) {
+                        const float* src = CT + (int64_t)tu[u] * k + cq;
+                        if (cq + 0 < g1) g[u].x = src[0];
+                        if (cq + 1 < g1) g[u].y = src[1];
+                        if (cq + 2 < g1) g[u].z = src[2];
+                        if (cq + 3 < g1) g[u].w = src[3];
+                    }
+                }
+            }
+            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                a.x = fmaf(xu[u], g[u].x, a.x);
+                a.y = fmaf(xu[u], g[u].y, a.y);
+                a.z = fmaf(xu[u], g[u].z, a.z);
+                a.w = fmaf(xu[u], g[u].w, a.w);
+            }
+#pragma unroll
+            for (int o = Q; o < 64; o <<= 1) a = add4(a, shfl_xor4(a, o));
+            if (sub == 0) sh.P[par][wv][q] = a;
+            bw_bar();
+            if (threadIdx.x < kCols) {
+                const int c = threadIdx.x;
+                const float* pc = reinterpret_cast<const float*>(&sh.P[par][0][0]) + c;
+                float st = pc[0];
+#pragma unroll
+                for (int v = 1; v < kSoftThreads / 64; ++v) st = st + pc[v * kCols];
+                const float ds = c < w ? neg_g_over_tau * expf(st * inv_tau - l) : 0.0f;
+                sh.D[par][c] = ds;
+                if (c < w) dsrow[cb + c] = ds;
+            }
+            bw_bar();
+            const float4 d = *reinterpret_cast<const float4*>(&sh.D[par][4 * q]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float p = d.x * g[u].x;
+                p = fmaf(d.y, g[u].y, p);
+                p = fmaf(d.z, g[u].z, p);
+                p = fmaf(d.w, g[u].w, p);
+                dxr[u] += row16_sum(p);
+            }
+            par ^= 1;
+        }
+        if (q == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (tu[u] >= 0) dxrow[(int64_t)(u * kTpr + (64 / Q) * wv + sub) * kSoftGroups] = dxr[u];
+        }
     }
 }
 
@@ -540,8 +648,14 @@ hipError_t soft_bwd_rows(int64_t c0, int64_t c1, int64_t p0, int64_t p1, const i
     const int per_cu = std::max(1, (int)(160 * 1024 / sizeof(BwLds<kBwW>)));
     const int64_t per_group = std::min<int64_t>(c1 - c0, (int64_t)n_cu * per_cu / kSoftGroups);
     // short rows, then the rest (each kernel skips the other's rows)
-    hipLaunchKernelGGL((k_soft_bwd_rows_pf<kBwW>), dim3((unsigned)(per_group * kSoftGroups)), dim3(kSoftThreads), 0, s,
-                       c0, c1, rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxp);
+    {
+        const void* fn = (const void*)k_soft_bwd_rows_reg<kRegQ, kRegU>;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kSoftThreads, 0) != hipSuccess || nb < 1) nb = 1;
+        const int64_t pg = std::max<int64_t>(1, std::min<int64_t>(c1 - c0, (int64_t)n_cu * nb / kSoftGroups));
+        hipLaunchKernelGGL((k_soft_bwd_rows_reg<kRegQ, kRegU>), dim3((unsigned)(pg * kSoftGroups)), dim3(kSoftThreads),
+                           0, s, c0, c1, rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxp);
+    }
     hipLaunchKernelGGL((k_soft_bwd_rows<kBwW>), dim3((unsigned)(per_group * kSoftGroups)), dim3(kSoftThreads), 0, s, c0,
                        c1, rp, col, xv, CT, k, 1.0f / tau, -grad / tau, lse, dS, dxp);
     if (p1 > p0)

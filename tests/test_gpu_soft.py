@@ -63,9 +63,10 @@ def test_soft_forward_backward_match_oracle(n, d, k):
 
 @pytest.mark.parametrize("k", [300, 299])
 def test_soft_rows_longer_than_one_lds_batch(k):
-    # ~300 terms per row: the backward stages a row's centroid slices in
-    # batches of 144 terms (two or three per row); k = 300 ends on a partial
-    # 128-column block, k = 299 also takes the unaligned gathers
+    # ~300 terms per row: the backward's long-row kernel stages a row's
+    # centroid slices in batches of 136 terms (two or three per row); k = 300
+    # ends on a partial 64-column block, k = 299 also takes the unaligned
+    # gathers
     log("soft long rows k=%d" % k)
     c, C = _case(120, 2000, k, seed=77 + k, lam=300)
     assert np.diff(c.row_ptr).max() > 288
@@ -76,6 +77,26 @@ def test_soft_rows_longer_than_one_lds_batch(k):
     np.testing.assert_allclose(lse.cpu().numpy(), lse_ref, rtol=0, atol=5e-4)
     dC, dX = ctx.soft_assign_bwd(X, Cg, TAU, lse, 1.3)
     dC_ref, dX_ref = oracle.soft_backward(c, C.astype(np.float64), TAU, 1.3, lse_ref)
+    np.testing.assert_allclose(dX.cpu().numpy(), dX_ref, rtol=2e-3, atol=1e-9)
+    np.testing.assert_allclose(dC.cpu().numpy(), dC_ref, rtol=2e-3, atol=1e-7)
+
+
+@pytest.mark.parametrize("k", [512, 299])
+def test_soft_rows_on_both_sides_of_the_register_limit(k):
+    # Poisson(128) rows: rows of at most 128 terms go to the register-held
+    # rows kernel, longer ones to the LDS-staged one, in the same call
+    log("soft mixed rows k=%d" % k)
+    c, C = _case(600, 3000, k, seed=91 + k, lam=128)
+    lens = np.diff(c.row_ptr)
+    assert (lens <= 128).sum() > 100 and (lens > 128).sum() > 100
+    assert 128 in lens and 129 in lens
+    X, Cg = _dev(c, C)
+    ctx = _ctx()
+    lse, _ = ctx.soft_assign_fwd(X, Cg, TAU)
+    lse_ref = oracle.soft_forward(c, C.astype(np.float64), TAU)
+    np.testing.assert_allclose(lse.cpu().numpy(), lse_ref, rtol=0, atol=5e-4)
+    dC, dX = ctx.soft_assign_bwd(X, Cg, TAU, lse, 0.6)
+    dC_ref, dX_ref = oracle.soft_backward(c, C.astype(np.float64), TAU, 0.6, lse_ref)
     np.testing.assert_allclose(dX.cpu().numpy(), dX_ref, rtol=2e-3, atol=1e-9)
     np.testing.assert_allclose(dC.cpu().numpy(), dC_ref, rtol=2e-3, atol=1e-7)
 
