@@ -22,10 +22,7 @@
 namespace sivf {
 
 constexpr int kSoftThreads = 256;
-constexpr int kSoftCols = 16;                       // dC pass: columns per thread per chunk
-constexpr int kSoftChunk = kSoftThreads * kSoftCols;  // 4096 columns per chunk
 constexpr int kSoftTermsInLds = 256;                // forward: row entries staged per pass
-constexpr int kDctRows = 4;                         // dS rows in flight per dC step
 
 // ---------------------------------------------------------------- transpose
 // out[c][r] = in[r][c] for an R x Cn row-major matrix; 64x64 tiles via LDS.
@@ -75,9 +72,6 @@ __device__ inline float block_sum_f32(float v, float* sh) {
     for (int w = 0; w < kSoftThreads / 64; ++w) r += sh[w];
     return r;
 }
-
-// Column index of this thread's q-th value (q = 0..15) inside a 4096 chunk.
-__device__ inline int soft_col(int q) { return (q >> 2) * (kSoftThreads * 4) + threadIdx.x * 4 + (q & 3); }
 
 // ---------------------------------------------------------------- forward by column groups
 // Workgroups are dispatched to the 8 XCDs in turn, so workgroup b runs on XCD
@@ -737,14 +731,14 @@ hipError_t soft_csc(int64_t N, int64_t d, int64_t nnz, const int64_t* rp, const 
 // CSC list.  Zipf term frequencies make a few ranges as long as the chunk
 // (the hottest terms occur in nearly every row) while most hold a handful of
 // rows, so one workgroup per term would leave the long ranges to a few
-// workgroups.  Ranges of at most `piece` rows are summed by one workgroup
-// straight into dCT[t]; longer ones are cut into pieces of `piece` rows, each
-// summed by its own workgroup into a partial row, and the partial rows are
-// then added into dCT[t] piece by piece in ascending order.  Every sum has a
-// fixed order, so the result is run-to-run identical.  A long range of len
-// rows has ceil(len / piece) < 2 len / piece pieces, so a chunk with nnz_c
-// nonzeros has fewer than 2 nnz_c / piece of them: the host sizes the partial
-// rows and the piece length from that bound.
+// workgroups.  Ranges of at most `piece` rows are summed by one workgroup per
+// column group straight into dCT[t]; longer ones are cut into pieces of
+// `piece` rows, each summed by its own workgroups into a partial row, and the
+// partial rows are then added into dCT[t] piece by piece in ascending order.
+// Every sum has a fixed order, so the result is run-to-run identical.  A long
+// range of len rows has ceil(len / piece) < 2 len / piece pieces, so a chunk
+// with nnz_c nonzeros has fewer than 2 nnz_c / piece of them: the host sizes
+// the partial rows and the piece length from that bound.
 
 // lo/hi of every term's rows inside [c0, c1); np[t] = pieces of a long range (else 0)
 __global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, const int64_t* __restrict__ colptr,
@@ -799,106 +793,128 @@ hipError_t soft_chunk_offsets(const int64_t* rp, int64_t n, int64_t rc, int64_t 
     return hipGetLastError();
 }
 
-// acc[q] (+)= sum over CSC entries [p0, p1) (rows ascending) of v * dS row
-__device__ inline void dct_sum(int32_t k, int64_t c0, int64_t ch0, int64_t p0, int64_t p1,
-                               const int32_t* __restrict__ xt_row, const float* __restrict__ xt_val,
-                               const float* __restrict__ dS, float acc[kSoftCols]) {
-    const bool full = ch0 + kSoftChunk <= k && (k & 3) == 0;  // float4 gathers stay 16-byte aligned
-    if (full) {
-        // kDctRows rows per step: their ids, then all their gathers, are issued
-        // before the first multiply-add, which still runs in ascending row order
-        for (int64_t q0 = p0; q0 < p1; q0 += kDctRows) {
-            const int m = (int)min((int64_t)kDctRows, p1 - q0);
-            int64_t ro[kDctRows];
-            float vv[kDctRows];
+// Column groups as in the forward: workgroup b takes column group b mod 8
+// (one per XCD), so each XCD's L2 holds only its eighth of every dS row
+// (backward 113 -> 107 ms at N = 262,144, k = 4,096 against workgroups
+// spanning all k columns).  128 threads, four columns each: 512 columns per
+// pass of a group.  Each column is summed over the rows in ascending order,
+// one fused multiply-add per row.
+constexpr int kDctThreads = 128;
+constexpr int kDctRowsG = 8;   // rows whose gathers are in flight together
+
+// acc (+)= sum over CSC entries [p0, p1) (rows ascending) of v * dS[row][cq .. cq+3]
+__device__ inline void dct_sum_g(int32_t k, int64_t c0, int64_t cq, int64_t g1, int64_t p0, int64_t p1,
+                                 const int32_t* __restrict__ xt_row, const float* __restrict__ xt_val,
+                                 const float* __restrict__ dS, float4& acc) {
+    if ((k & 3) == 0 && cq + 4 <= g1) {
+        for (int64_t q0 = p0; q0 < p1; q0 += kDctRowsG) {
+            const int m = (int)min((int64_t)kDctRowsG, p1 - q0);
+            int64_t ro[kDctRowsG];
+            float vv[kDctRowsG];
 #pragma unroll
-            for (int u = 0; u < kDctRows; ++u) {
+            for (int u = 0; u < kDctRowsG; ++u) {
                 const bool in = u < m;
-                ro[u] = (int64_t)(xt_row[in ? q0 + u : q0] - c0) * k + ch0;
+                ro[u] = (int64_t)(xt_row[in ? q0 + u : q0] - c0) * k + cq;
                 vv[u] = in ? xt_val[q0 + u] : 0.0f;
             }
-            float4 g[kDctRows][4];
+            float4 g[kDctRowsG];
 #pragma unroll
-            for (int u = 0; u < kDctRows; ++u)
+            for (int u = 0; u < kDctRowsG; ++u) g[u] = *reinterpret_cast<const float4*>(dS + ro[u]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    g[u][q] = *reinterpret_cast<const float4*>(dS + ro[u] + q * (kSoftThreads * 4) + threadIdx.x * 4);
-#pragma unroll
-            for (int u = 0; u < kDctRows; ++u) {
+            for (int u = 0; u < kDctRowsG; ++u) {
                 if (u < m) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        acc[4 * q + 0] = fmaf(vv[u], g[u][q].x, acc[4 * q + 0]);
-                        acc[4 * q + 1] = fmaf(vv[u], g[u][q].y, acc[4 * q + 1]);
-                        acc[4 * q + 2] = fmaf(vv[u], g[u][q].z, acc[4 * q + 2]);
-                        acc[4 * q + 3] = fmaf(vv[u], g[u][q].w, acc[4 * q + 3]);
-                    }
+                    acc.x = fmaf(vv[u], g[u].x, acc.x);
+                    acc.y = fmaf(vv[u], g[u].y, acc.y);
+                    acc.z = fmaf(vv[u], g[u].z, acc.z);
+                    acc.w = fmaf(vv[u], g[u].w, acc.w);
                 }
             }
         }
-    } else {
+    } else if (cq < g1) {
         for (int64_t p = p0; p < p1; ++p) {
             const float v = xt_val[p];
-            const float* row = dS + (int64_t)(xt_row[p] - c0) * k + ch0;
-#pragma unroll
-            for (int q = 0; q < kSoftCols; ++q)
-                if (ch0 + soft_col(q) < k) acc[q] = fmaf(v, row[soft_col(q)], acc[q]);
+            const float* row = dS + (int64_t)(xt_row[p] - c0) * k + cq;
+            acc.x = fmaf(v, row[0], acc.x);
+            if (cq + 1 < g1) acc.y = fmaf(v, row[1], acc.y);
+            if (cq + 2 < g1) acc.z = fmaf(v, row[2], acc.z);
+            if (cq + 3 < g1) acc.w = fmaf(v, row[3], acc.w);
         }
     }
 }
 
-// short ranges: one workgroup per term, straight into dCT[t] (zeroed on the
-// first chunk when the term has no row in it)
-__global__ __launch_bounds__(kSoftThreads) void k_dct_short(int64_t d, int32_t k, int64_t c0, int first, int64_t piece,
-                                                            const int64_t* __restrict__ lo_t,
-                                                            const int64_t* __restrict__ hi_t,
-                                                            const int32_t* __restrict__ xt_row,
-                                                            const float* __restrict__ xt_val,
-                                                            const float* __restrict__ dS, float* __restrict__ dCT) {
-    for (int64_t t = blockIdx.x; t < d; t += gridDim.x) {
+__device__ inline float4 load4_lim(const float* p, int64_t cq, int64_t g1, bool vec) {
+    if (vec) return *reinterpret_cast<const float4*>(p);
+    float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (cq + 0 < g1) a.x = p[0];
+    if (cq + 1 < g1) a.y = p[1];
+    if (cq + 2 < g1) a.z = p[2];
+    if (cq + 3 < g1) a.w = p[3];
+    return a;
+}
+
+__device__ inline void store4_lim(float* p, float4 a, int64_t cq, int64_t g1, bool vec) {
+    if (vec) {
+        *reinterpret_cast<float4*>(p) = a;
+        return;
+    }
+    if (cq + 0 < g1) p[0] = a.x;
+    if (cq + 1 < g1) p[1] = a.y;
+    if (cq + 2 < g1) p[2] = a.z;
+    if (cq + 3 < g1) p[3] = a.w;
+}
+
+// short ranges: one workgroup per (term, column group), straight into dCT[t]
+// (zeroed on the first chunk when the term has no row in it)
+__global__ __launch_bounds__(kDctThreads) void k_dct_short(int64_t d, int32_t k, int64_t c0, int first, int64_t piece,
+                                                           const int64_t* __restrict__ lo_t,
+                                                           const int64_t* __restrict__ hi_t,
+                                                           const int32_t* __restrict__ xt_row,
+                                                           const float* __restrict__ xt_val,
+                                                           const float* __restrict__ dS, float* __restrict__ dCT) {
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
+    for (int64_t t = blockIdx.x / kSoftGroups; t < d; t += gridDim.x / kSoftGroups) {
         const int64_t lo = lo_t[t], hi = hi_t[t];
         if (hi - lo > piece) continue;   // a long range: summed in pieces
         if (lo == hi && !first) continue;
-        for (int64_t ch0 = 0; ch0 < k; ch0 += kSoftChunk) {
-            float acc[kSoftCols];
-            float* out = dCT + t * (int64_t)k + ch0;
-#pragma unroll
-            for (int q = 0; q < kSoftCols; ++q) {
-                const int64_t c = ch0 + soft_col(q);
-                acc[q] = (first || c >= k) ? 0.0f : out[soft_col(q)];
-            }
-            dct_sum(k, c0, ch0, lo, hi, xt_row, xt_val, dS, acc);
-#pragma unroll
-            for (int q = 0; q < kSoftCols; ++q)
-                if (ch0 + soft_col(q) < k) out[soft_col(q)] = acc[q];
+        for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
+            const int64_t cq = cb + 4 * threadIdx.x;
+            if (cq >= g1) continue;
+            const bool vec = (k & 3) == 0 && cq + 4 <= g1;
+            float* out = dCT + t * (int64_t)k + cq;
+            float4 acc = first ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : load4_lim(out, cq, g1, vec);
+            dct_sum_g(k, c0, cq, g1, lo, hi, xt_row, xt_val, dS, acc);
+            store4_lim(out, acc, cq, g1, vec);
         }
     }
 }
 
-// one piece of a long range into its partial row
-__global__ __launch_bounds__(kSoftThreads) void k_dct_piece(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
-                                                            int64_t piece,
-                                                            const int32_t* __restrict__ item,
-                                                            const int64_t* __restrict__ pstart,
-                                                            const int64_t* __restrict__ lo_t,
-                                                            const int64_t* __restrict__ hi_t,
-                                                            const int32_t* __restrict__ xt_row,
-                                                            const float* __restrict__ xt_val,
-                                                            const float* __restrict__ dS, float* __restrict__ part) {
+// one piece of a long range into its partial row, one column group per workgroup
+__global__ __launch_bounds__(kDctThreads) void k_dct_piece(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
+                                                           int64_t piece,
+                                                           const int32_t* __restrict__ item,
+                                                           const int64_t* __restrict__ pstart,
+                                                           const int64_t* __restrict__ lo_t,
+                                                           const int64_t* __restrict__ hi_t,
+                                                           const int32_t* __restrict__ xt_row,
+                                                           const float* __restrict__ xt_val,
+                                                           const float* __restrict__ dS, float* __restrict__ part) {
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
     const int64_t npieces = min(pstart[d], max_pieces);   // the host bound caps the device count
-    for (int64_t q = blockIdx.x; q < npieces; q += gridDim.x) {
+    for (int64_t q = blockIdx.x / kSoftGroups; q < npieces; q += gridDim.x / kSoftGroups) {
         const int32_t t = item[q];
         const int64_t j = q - pstart[t];
         const int64_t p0 = lo_t[t] + j * piece, p1 = min(hi_t[t], p0 + piece);
-        for (int64_t ch0 = 0; ch0 < k; ch0 += kSoftChunk) {
-            float acc[kSoftCols];
-#pragma unroll
-            for (int qq = 0; qq < kSoftCols; ++qq) acc[qq] = 0.0f;
-            dct_sum(k, c0, ch0, p0, p1, xt_row, xt_val, dS, acc);
-            float* out = part + q * (int64_t)k + ch0;
-#pragma unroll
-            for (int qq = 0; qq < kSoftCols; ++qq)
-                if (ch0 + soft_col(qq) < k) out[soft_col(qq)] = acc[qq];
+        for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
+            const int64_t cq = cb + 4 * threadIdx.x;
+            if (cq >= g1) continue;
+            const bool vec = (k & 3) == 0 && cq + 4 <= g1;
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            dct_sum_g(k, c0, cq, g1, p0, p1, xt_row, xt_val, dS, acc);
+            store4_lim(part + q * (int64_t)k + cq, acc, cq, g1, vec);
         }
     }
 }
@@ -932,16 +948,15 @@ hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, con
     hipError_t e = exclusive_scan_i64(w.np, w.pstart, d, w.scan_ws, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dct_items, dim3(tb), dim3(256), 0, s, d, w.max_pieces, w.np, w.pstart, w.item);
-    const int64_t grid = std::min<int64_t>(d, (int64_t)n_cu * 16);
-    hipLaunchKernelGGL(k_dct_short, dim3((unsigned)grid), dim3(kSoftThreads), 0, s, d, k, c0, first, w.piece, w.lo,
-                       w.hi,
-                       xt_row, xt_val, dS, dCT);
+    const int64_t grid = std::min<int64_t>(d, (int64_t)n_cu * 16) * kSoftGroups;
+    hipLaunchKernelGGL(k_dct_short, dim3((unsigned)grid), dim3(kDctThreads), 0, s, d, k, c0, first, w.piece, w.lo,
+                       w.hi, xt_row, xt_val, dS, dCT);
     // pieces: at most max_pieces (a bound from the chunk's nonzeros), the
     // exact count is pstart[d] on the device
     if (w.max_pieces > 0) {
         const int64_t pg = std::min<int64_t>(w.max_pieces, (int64_t)n_cu * 16);
-        hipLaunchKernelGGL(k_dct_piece, dim3((unsigned)pg), dim3(kSoftThreads), 0, s, d, w.max_pieces, k, c0, w.piece,
-                           w.item, w.pstart, w.lo, w.hi, xt_row, xt_val, dS, w.part);
+        hipLaunchKernelGGL(k_dct_piece, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d, w.max_pieces, k,
+                           c0, w.piece, w.item, w.pstart, w.lo, w.hi, xt_row, xt_val, dS, w.part);
         hipLaunchKernelGGL(k_dct_combine, dim3((unsigned)pg), dim3(256), 0, s, d, w.max_pieces, k, first, w.item, w.np,
                            w.pstart, w.part, dCT);
     }
