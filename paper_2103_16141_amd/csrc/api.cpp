@@ -1112,11 +1112,23 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         // within 512 MiB
         const int64_t cap = 512ll << 20;
         dw.piece = std::max<int64_t>(256, (2 * nnz_max * (int64_t)k * 4 + cap - 1) / cap);
-        dw.max_pieces = 2 * nnz_max / dw.piece + 1;
+        // hot terms (more than four row blocks' worth of entries) are cut at
+        // row blocks of 512 rows, or more where their partial rows would
+        // pass 512 MiB
+        int64_t hot_pieces = 0;
+        for (dw.blk_rows = 512;; dw.blk_rows *= 2) {
+            dw.hot_min = 4 * dw.blk_rows;
+            hot_pieces = nnz_max / (dw.hot_min + 1) * ((rc + dw.blk_rows - 1) / dw.blk_rows);
+            if (hot_pieces * (int64_t)k * 4 <= cap || dw.blk_rows >= rc) break;
+        }
+        dw.max_pieces = 2 * nnz_max / dw.piece + 1 + hot_pieces;
         STCHK(ws(ctx, "dct_lo", d, &dw.lo));
         STCHK(ws(ctx, "dct_hi", d, &dw.hi));
         STCHK(ws(ctx, "dct_np", d, &dw.np));
         STCHK(ws(ctx, "dct_pstart", d + 1, &dw.pstart));
+        STCHK(ws(ctx, "dct_hflag", d, &dw.hflag));
+        STCHK(ws(ctx, "dct_hscan", d + 1, &dw.hscan));
+        STCHK(ws(ctx, "dct_hot", d, &dw.hot));
         dw.scan_ws = sws;
         STCHK(ws(ctx, "dct_item", dw.max_pieces, &dw.item));
         STCHK(ws(ctx, "dct_part", dw.max_pieces * (int64_t)k, &dw.part));

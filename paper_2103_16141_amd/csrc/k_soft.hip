@@ -731,19 +731,28 @@ hipError_t soft_csc(int64_t N, int64_t d, int64_t nnz, const int64_t* rp, const 
 // CSC list.  Zipf term frequencies make a few ranges as long as the chunk
 // (the hottest terms occur in nearly every row) while most hold a handful of
 // rows, so one workgroup per term would leave the long ranges to a few
-// workgroups.  Ranges of at most `piece` rows are summed by one workgroup per
-// column group straight into dCT[t]; longer ones are cut into pieces of
-// `piece` rows, each summed by its own workgroups into a partial row, and the
-// partial rows are then added into dCT[t] piece by piece in ascending order.
-// Every sum has a fixed order, so the result is run-to-run identical.  A long
-// range of len rows has ceil(len / piece) < 2 len / piece pieces, so a chunk
-// with nnz_c nonzeros has fewer than 2 nnz_c / piece of them: the host sizes
-// the partial rows and the piece length from that bound.
+// workgroups.  Three kinds of range:
+//   * at most `piece` entries: summed by one workgroup per column group
+//     straight into dCT[t] (k_dct_short);
+//   * more than hot_min entries (a hot term): cut at the chunk's row blocks
+//     of blk_rows rows, one piece per block, and the pieces are run block by
+//     block across all hot terms (k_dct_rowblock), so the workgroups of an
+//     XCD read the same block of dS rows at the same time and mostly from
+//     L2;
+//   * the rest: cut into pieces of `piece` entries (k_dct_piece).
+// Each piece is summed into a partial row, and k_dct_combine adds a term's
+// partial rows into dCT[t] in piece order.  Every sum has a fixed order, so
+// the result is run-to-run identical.  Bounds for sizing the partial rows: a
+// range of len > piece entries that is not hot has ceil(len / piece) <
+// 2 len / piece pieces, and a chunk with nnz_c nonzeros has at most
+// nnz_c / (hot_min + 1) hot terms of nblk pieces each.
 
-// lo/hi of every term's rows inside [c0, c1); np[t] = pieces of a long range (else 0)
-__global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, const int64_t* __restrict__ colptr,
-                           const int32_t* __restrict__ xt_row, int64_t* __restrict__ lo_out,
-                           int64_t* __restrict__ hi_out, int64_t* __restrict__ np) {
+// lo/hi of every term's rows inside [c0, c1); np[t] = pieces of a long range
+// (else 0); hflag[t] = 1 for a hot term
+__global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, int64_t hot_min, int64_t nblk,
+                           const int64_t* __restrict__ colptr, const int32_t* __restrict__ xt_row,
+                           int64_t* __restrict__ lo_out, int64_t* __restrict__ hi_out, int64_t* __restrict__ np,
+                           int64_t* __restrict__ hflag) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= d) return;
     const int64_t b = colptr[t], e = colptr[t + 1];
@@ -770,7 +779,31 @@ __global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, con
     }
     lo_out[t] = lo;
     hi_out[t] = hi;
-    np[t] = hi - lo > piece ? (hi - lo + piece - 1) / piece : 0;
+    const int64_t n = hi - lo;
+    hflag[t] = n > hot_min ? 1 : 0;
+    np[t] = n > hot_min ? nblk : (n > piece ? (n + piece - 1) / piece : 0);
+}
+
+// hot[hscan[t]] = t for the hot terms
+__global__ void k_dct_hot(int64_t d, const int64_t* __restrict__ hflag, const int64_t* __restrict__ hscan,
+                          int32_t* __restrict__ hot) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < d && hflag[t]) hot[hscan[t]] = (int32_t)t;
+}
+
+// first entry in [lo, hi) of the ascending xt_row whose row is >= r
+__device__ inline int64_t row_lower_bound(const int32_t* __restrict__ xt_row, int64_t lo, int64_t hi, int64_t r) {
+    int64_t len = hi - lo;
+    while (len > 0) {
+        const int64_t half = len >> 1;
+        if (xt_row[lo + half] < r) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    return lo;
 }
 
 // item[pstart[t] + j] = t for the pieces j of each long range
@@ -865,7 +898,8 @@ __device__ inline void store4_lim(float* p, float4 a, int64_t cq, int64_t g1, bo
 
 // short ranges: one workgroup per (term, column group), straight into dCT[t]
 // (zeroed on the first chunk when the term has no row in it)
-__global__ __launch_bounds__(kDctThreads) void k_dct_short(int64_t d, int32_t k, int64_t c0, int first, int64_t piece,
+__global__ __launch_bounds__(kDctThreads) void k_dct_short(int64_t d, int32_t k, int64_t c0, int first,
+                                                           const int64_t* __restrict__ np,
                                                            const int64_t* __restrict__ lo_t,
                                                            const int64_t* __restrict__ hi_t,
                                                            const int32_t* __restrict__ xt_row,
@@ -876,7 +910,7 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_short(int64_t d, int32_t k,
     const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
     for (int64_t t = blockIdx.x / kSoftGroups; t < d; t += gridDim.x / kSoftGroups) {
         const int64_t lo = lo_t[t], hi = hi_t[t];
-        if (hi - lo > piece) continue;   // a long range: summed in pieces
+        if (np[t] > 0) continue;   // a long range: summed in pieces
         if (lo == hi && !first) continue;
         for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
             const int64_t cq = cb + 4 * threadIdx.x;
@@ -892,7 +926,7 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_short(int64_t d, int32_t k,
 
 // one piece of a long range into its partial row, one column group per workgroup
 __global__ __launch_bounds__(kDctThreads) void k_dct_piece(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
-                                                           int64_t piece,
+                                                           int64_t piece, int64_t hot_min,
                                                            const int32_t* __restrict__ item,
                                                            const int64_t* __restrict__ pstart,
                                                            const int64_t* __restrict__ lo_t,
@@ -906,8 +940,45 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_piece(int64_t d, int64_t ma
     const int64_t npieces = min(pstart[d], max_pieces);   // the host bound caps the device count
     for (int64_t q = blockIdx.x / kSoftGroups; q < npieces; q += gridDim.x / kSoftGroups) {
         const int32_t t = item[q];
+        if (hi_t[t] - lo_t[t] > hot_min) continue;   // a hot term: k_dct_rowblock
         const int64_t j = q - pstart[t];
         const int64_t p0 = lo_t[t] + j * piece, p1 = min(hi_t[t], p0 + piece);
+        for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
+            const int64_t cq = cb + 4 * threadIdx.x;
+            if (cq >= g1) continue;
+            const bool vec = (k & 3) == 0 && cq + 4 <= g1;
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            dct_sum_g(k, c0, cq, g1, p0, p1, xt_row, xt_val, dS, acc);
+            store4_lim(part + q * (int64_t)k + cq, acc, cq, g1, vec);
+        }
+    }
+}
+
+// the hot terms' pieces, block by block: piece o covers row block o / H of
+// hot term o mod H (H hot terms), so concurrent workgroups read one block of
+// dS rows; one column group per workgroup
+__global__ __launch_bounds__(kDctThreads) void k_dct_rowblock(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
+                                                              int64_t c1, int64_t blk_rows, int64_t nblk,
+                                                              const int32_t* __restrict__ hot,
+                                                              const int64_t* __restrict__ hscan,
+                                                              const int64_t* __restrict__ pstart,
+                                                              const int64_t* __restrict__ lo_t,
+                                                              const int64_t* __restrict__ hi_t,
+                                                              const int32_t* __restrict__ xt_row,
+                                                              const float* __restrict__ xt_val,
+                                                              const float* __restrict__ dS, float* __restrict__ part) {
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
+    const int64_t H = hscan[d];
+    for (int64_t o = blockIdx.x / kSoftGroups; o < H * nblk; o += gridDim.x / kSoftGroups) {
+        const int64_t j = o / H;
+        const int32_t t = hot[o - j * H];
+        const int64_t q = pstart[t] + j;
+        if (q >= max_pieces) continue;   // cannot happen: the host bound holds
+        const int64_t r0 = c0 + j * blk_rows, r1 = min(c1, r0 + blk_rows);
+        const int64_t p0 = row_lower_bound(xt_row, lo_t[t], hi_t[t], r0);
+        const int64_t p1 = row_lower_bound(xt_row, p0, hi_t[t], r1);
         for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
             const int64_t cq = cb + 4 * threadIdx.x;
             if (cq >= g1) continue;
@@ -944,19 +1015,27 @@ hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, con
                     hipStream_t s) {
     if (d <= 0) return hipSuccess;
     const unsigned tb = (unsigned)((d + 255) / 256);
-    hipLaunchKernelGGL(k_dct_plan, dim3(tb), dim3(256), 0, s, d, c0, c1, w.piece, colptr, xt_row, w.lo, w.hi, w.np);
+    const int64_t nblk = (c1 - c0 + w.blk_rows - 1) / w.blk_rows;
+    hipLaunchKernelGGL(k_dct_plan, dim3(tb), dim3(256), 0, s, d, c0, c1, w.piece, w.hot_min, nblk, colptr, xt_row, w.lo,
+                       w.hi, w.np, w.hflag);
     hipError_t e = exclusive_scan_i64(w.np, w.pstart, d, w.scan_ws, s);
     if (e != hipSuccess) return e;
+    e = exclusive_scan_i64(w.hflag, w.hscan, d, w.scan_ws, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dct_items, dim3(tb), dim3(256), 0, s, d, w.max_pieces, w.np, w.pstart, w.item);
+    hipLaunchKernelGGL(k_dct_hot, dim3(tb), dim3(256), 0, s, d, w.hflag, w.hscan, w.hot);
     const int64_t grid = std::min<int64_t>(d, (int64_t)n_cu * 16) * kSoftGroups;
-    hipLaunchKernelGGL(k_dct_short, dim3((unsigned)grid), dim3(kDctThreads), 0, s, d, k, c0, first, w.piece, w.lo,
+    hipLaunchKernelGGL(k_dct_short, dim3((unsigned)grid), dim3(kDctThreads), 0, s, d, k, c0, first, w.np, w.lo,
                        w.hi, xt_row, xt_val, dS, dCT);
     // pieces: at most max_pieces (a bound from the chunk's nonzeros), the
     // exact count is pstart[d] on the device
     if (w.max_pieces > 0) {
         const int64_t pg = std::min<int64_t>(w.max_pieces, (int64_t)n_cu * 16);
         hipLaunchKernelGGL(k_dct_piece, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d, w.max_pieces, k,
-                           c0, w.piece, w.item, w.pstart, w.lo, w.hi, xt_row, xt_val, dS, w.part);
+                           c0, w.piece, w.hot_min, w.item, w.pstart, w.lo, w.hi, xt_row, xt_val, dS, w.part);
+        hipLaunchKernelGGL(k_dct_rowblock, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d,
+                           w.max_pieces, k, c0, c1, w.blk_rows, nblk, w.hot, w.hscan, w.pstart, w.lo, w.hi, xt_row,
+                           xt_val, dS, w.part);
         hipLaunchKernelGGL(k_dct_combine, dim3((unsigned)pg), dim3(256), 0, s, d, w.max_pieces, k, first, w.item, w.np,
                            w.pstart, w.part, dCT);
     }

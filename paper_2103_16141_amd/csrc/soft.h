@@ -22,13 +22,18 @@ hipError_t soft_chunk_offsets(const int64_t* rp, int64_t n, int64_t rc, int64_t 
 struct DctWs {
     int64_t* lo;        // [d] first CSC entry of the chunk's rows
     int64_t* hi;        // [d] one past the last
-    int64_t* np;        // [d] pieces of a range longer than `piece` rows, else 0
+    int64_t* np;        // [d] pieces of a long range (see soft_dct), else 0
     int64_t* pstart;    // [d + 1] exclusive scan of np
+    int64_t* hflag;     // [d] 1 for a hot term (range longer than hot_min entries)
+    int64_t* hscan;     // [d + 1] exclusive scan of hflag
+    int32_t* hot;       // [d] the hot terms, ascending
     int64_t* scan_ws;   // scan_ws_elems(d)
     int32_t* item;      // [max_pieces] term of each piece
     float* part;        // [max_pieces * k] partial rows
-    int64_t max_pieces; // bound on the pieces of any chunk (fewer than 2 nnz_c / piece)
-    int64_t piece;      // rows per piece
+    int64_t max_pieces; // bound on the pieces of any chunk
+    int64_t piece;      // entries per piece of a long range that is not hot
+    int64_t hot_min;    // entries above which a range is cut at row blocks
+    int64_t blk_rows;   // rows per row block
 };
 hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, const int64_t* colptr,
                     const int32_t* xt_row, const float* xt_val, const float* dS, float* dCT, DctWs w, int n_cu,

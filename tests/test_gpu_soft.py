@@ -101,6 +101,32 @@ def test_soft_rows_on_both_sides_of_the_register_limit(k):
     np.testing.assert_allclose(dC.cpu().numpy(), dC_ref, rtol=2e-3, atol=1e-7)
 
 
+@pytest.mark.parametrize("k", [16384, 16383])
+def test_soft_hot_terms_cut_at_row_blocks(k):
+    # 40 terms, 20 per row: at k = 16384 the dS chunks hold 4096 rows, and in
+    # the first one 15 terms have more than 2048 entries (summed in 512-row
+    # blocks across terms), 25 have 257..2048 (256-entry pieces); the second
+    # chunk (1904 rows) has none above 2048; k = 16383 takes the unaligned
+    # gathers
+    log("soft hot terms k=%d" % k)
+    c = synth.make_corpus(6000, 40, 20, 1.1, np.float32, seed=123)
+    C = synth.dense_centroids(c, np.arange(k) % c.n, noise=1e-3, seed=7)
+    rc = (64 << 20) // k
+    cnt = np.bincount(c.col[:c.row_ptr[rc]], minlength=c.d)
+    assert rc == 4096 and (cnt > 2048).sum() >= 10 and ((cnt > 256) & (cnt <= 2048)).sum() >= 10
+    X, Cg = _dev(c, C)
+    ctx = _ctx()
+    lse, _ = ctx.soft_assign_fwd(X, Cg, TAU)
+    lse_ref = oracle.soft_forward(c, C.astype(np.float64), TAU)
+    np.testing.assert_allclose(lse.cpu().numpy(), lse_ref, rtol=0, atol=5e-4)
+    dC, dX = ctx.soft_assign_bwd(X, Cg, TAU, lse, 0.9)
+    dC_ref, dX_ref = oracle.soft_backward(c, C.astype(np.float64), TAU, 0.9, lse_ref)
+    np.testing.assert_allclose(dX.cpu().numpy(), dX_ref, rtol=2e-3, atol=1e-9)
+    np.testing.assert_allclose(dC.cpu().numpy(), dC_ref, rtol=2e-3, atol=1e-7)
+    again = ctx.soft_assign_bwd(X, Cg, TAU, lse, 0.9)
+    assert torch.equal(again[0], dC) and torch.equal(again[1], dX)
+
+
 def test_soft_backward_is_deterministic_and_partial_outputs():
     c, C = _case(800, 1200, 300, seed=3)
     X, Cg = _dev(c, C)
