@@ -990,22 +990,45 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_rowblock(int64_t d, int64_t
     }
 }
 
-// dCT[t] = (first ? 0 : dCT[t]) + partial rows of t's pieces, in piece order;
-// one workgroup per long-range term (found at its first piece), threads over columns
-__global__ void k_dct_combine(int64_t d, int64_t max_pieces, int32_t k, int first, const int32_t* __restrict__ item,
-                              const int64_t* __restrict__ np, const int64_t* __restrict__ pstart,
-                              const float* __restrict__ part, float* __restrict__ dCT) {
+// dCT[t] = (first ? 0 : dCT[t]) + partial rows of t's pieces, added in piece
+// order; one workgroup per (long-range term, column group), found at the
+// term's first piece; the loads of kCombineAhead partial rows are issued
+// before their adds
+constexpr int kCombineAhead = 8;
+
+__global__ __launch_bounds__(kDctThreads) void k_dct_combine(int64_t d, int64_t max_pieces, int32_t k, int first,
+                                                             const int32_t* __restrict__ item,
+                                                             const int64_t* __restrict__ np,
+                                                             const int64_t* __restrict__ pstart,
+                                                             const float* __restrict__ part,
+                                                             float* __restrict__ dCT) {
+    const int x = blockIdx.x % kSoftGroups;
+    const int64_t kc = soft_group_width(k);
+    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
     const int64_t npieces = min(pstart[d], max_pieces);
-    for (int64_t q = blockIdx.x; q < npieces; q += gridDim.x) {
+    for (int64_t q = blockIdx.x / kSoftGroups; q < npieces; q += gridDim.x / kSoftGroups) {
         const int32_t t = item[q];
         if (pstart[t] != q) continue;   // not the term's first piece
         const int64_t m = np[t];
         if (q + m > max_pieces) continue;   // cannot happen: the host bound holds
-        const float* pr = part + q * (int64_t)k;
-        for (int64_t c = threadIdx.x; c < k; c += blockDim.x) {
-            float acc = first ? 0.0f : dCT[t * (int64_t)k + c];
-            for (int64_t j = 0; j < m; ++j) acc = acc + pr[j * (int64_t)k + c];
-            dCT[t * (int64_t)k + c] = acc;
+        for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
+            const int64_t cq = cb + 4 * threadIdx.x;
+            if (cq >= g1) continue;
+            const bool vec = (k & 3) == 0 && cq + 4 <= g1;
+            float* out = dCT + t * (int64_t)k + cq;
+            float4 acc = first ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : load4_lim(out, cq, g1, vec);
+            const float* pr = part + q * (int64_t)k + cq;
+            for (int64_t j0 = 0; j0 < m; j0 += kCombineAhead) {
+                float4 v[kCombineAhead];
+#pragma unroll
+                for (int u = 0; u < kCombineAhead; ++u)
+                    v[u] = j0 + u < m ? load4_lim(pr + (j0 + u) * (int64_t)k, cq, g1, vec)
+                                      : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                for (int u = 0; u < kCombineAhead; ++u)
+                    if (j0 + u < m) acc = add4(acc, v[u]);
+            }
+            store4_lim(out, acc, cq, g1, vec);
         }
     }
 }
@@ -1036,8 +1059,8 @@ hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, con
         hipLaunchKernelGGL(k_dct_rowblock, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d,
                            w.max_pieces, k, c0, c1, w.blk_rows, nblk, w.hot, w.hscan, w.pstart, w.lo, w.hi, xt_row,
                            xt_val, dS, w.part);
-        hipLaunchKernelGGL(k_dct_combine, dim3((unsigned)pg), dim3(256), 0, s, d, w.max_pieces, k, first, w.item, w.np,
-                           w.pstart, w.part, dCT);
+        hipLaunchKernelGGL(k_dct_combine, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d, w.max_pieces,
+                           k, first, w.item, w.np, w.pstart, w.part, dCT);
     }
     return hipGetLastError();
 }
