@@ -239,7 +239,10 @@ hipError_t soft_forward(int64_t N, const int64_t* rp, const int32_t* col, const 
 
 // ---------------------------------------------------------------- backward, rows of one chunk
 // For rows [c0, c1): recompute S, write dS (row-major, k columns) and dX on the
-// row's nonzeros, reading each gathered C^T value once.
+// row's nonzeros, reading each gathered C^T value once.  Two kernels share the
+// rows: those of at most kRegTerms terms go to k_soft_bwd_rows_reg, which
+// keeps the gathered slices in registers (further below); the longer ones go
+// to k_soft_bwd_rows, which stages them in LDS as follows.
 //
 // Workgroup b takes column group b mod 8 (the forward's groups: one per XCD)
 // of each row it visits and walks the group's columns in blocks of W.  For a
