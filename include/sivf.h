@@ -315,7 +315,8 @@ sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
  *   dX_it = sum_j dS_ij C_jt on X's nonzeros -> dxval_out f32[nnz] (overwritten).
  * Either output may be NULL.  Deterministic (fixed summation order).
  * Workspace held by the ctx: C^T and dC^T (k * d floats each), X's column
- * copy (8 B per nonzero), dS for one chunk of rows (at most 256 MiB), dX
+ * copy (8 B per nonzero, built through 4 * d bytes of counts per 1024 rows),
+ * dS for one chunk of rows (at most 256 MiB), dX
  * partials (32 B per nonzero of a chunk), and the dC pass's partial rows
  * (at most about 1 GiB). */
 sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* C, int32_t k,
