@@ -316,9 +316,8 @@ sivf_status sivf_soft_assign_fwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
  * Either output may be NULL.  Deterministic (fixed summation order).
  * Workspace held by the ctx: C^T and dC^T (k * d floats each), X's column
  * copy (8 B per nonzero, built through 4 * d bytes of counts per 1024 rows),
- * dS for one chunk of rows (at most 256 MiB), dX
- * partials (32 B per nonzero of a chunk), and the dC pass's partial rows
- * (at most about 1 GiB). */
+ * dS for one chunk of rows (at most 256 MiB), dX partials (32 B per nonzero
+ * of a chunk), and the dC pass's partial rows (at most about 1 GiB). */
 sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* C, int32_t k,
                                  float tau, const float* lse, float grad_loss, float* dC_out,
                                  float* dxval_out);
