@@ -1107,21 +1107,14 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         STCHK(ws(ctx, "csc_val", std::max<int64_t>(Xc.nnz, 1), &xt_val));
         STCHK(ws(ctx, "scan_ws", scan_ws_elems(std::max<int64_t>(d + 1, n + 1)) + 8, &sws));
         HIPCHK(ctx, soft_csc(n, d, Xc.nnz, Xc.rp, Xc.col, (const float*)Xc.val, hist, cnt, colptr, sws, xt_row, xt_val, s));
-        // the largest chunk's nonzeros bound the pieces of the dC pass; the
-        // piece length grows past 256 rows only to keep the partial rows
-        // within 512 MiB
-        const int64_t cap = 512ll << 20;
-        dw.piece = std::max<int64_t>(256, (2 * nnz_max * (int64_t)k * 4 + cap - 1) / cap);
-        // hot terms (more than four row blocks' worth of entries) are cut at
-        // row blocks of 512 rows, or more where their partial rows would
-        // pass 512 MiB
-        int64_t hot_pieces = 0;
-        for (dw.blk_rows = 512;; dw.blk_rows *= 2) {
-            dw.hot_min = 4 * dw.blk_rows;
-            hot_pieces = nnz_max / (dw.hot_min + 1) * ((rc + dw.blk_rows - 1) / dw.blk_rows);
-            if (hot_pieces * (int64_t)k * 4 <= cap || dw.blk_rows >= rc) break;
-        }
-        dw.max_pieces = 2 * nnz_max / dw.piece + 1 + hot_pieces;
+        // ranges of at most 256 entries are summed whole; longer ones are cut
+        // at row blocks: 512 rows for ranges of more than 2048 entries (hot
+        // terms), 2048 rows for the rest (mid terms).  Every chunk's pieces
+        // are counted first, and the partial rows are sized for the largest.
+        dw.piece = 256;
+        dw.hot_min = 2048;
+        dw.blk_rows = 512;
+        dw.mid_blk_rows = 2048;
         STCHK(ws(ctx, "dct_lo", d, &dw.lo));
         STCHK(ws(ctx, "dct_hi", d, &dw.hi));
         STCHK(ws(ctx, "dct_np", d, &dw.np));
@@ -1129,9 +1122,22 @@ sivf_status sivf_soft_assign_bwd(sivf_ctx* ctx, const sivf_csr* X, const float* 
         STCHK(ws(ctx, "dct_hflag", d, &dw.hflag));
         STCHK(ws(ctx, "dct_hscan", d + 1, &dw.hscan));
         STCHK(ws(ctx, "dct_hot", d, &dw.hot));
+        STCHK(ws(ctx, "dct_mflag", d, &dw.mflag));
+        STCHK(ws(ctx, "dct_mscan", d + 1, &dw.mscan));
+        STCHK(ws(ctx, "dct_mid", d, &dw.mid));
         dw.scan_ws = sws;
-        STCHK(ws(ctx, "dct_item", dw.max_pieces, &dw.item));
-        STCHK(ws(ctx, "dct_part", dw.max_pieces * (int64_t)k, &dw.part));
+        int64_t* counts = nullptr;
+        STCHK(ws(ctx, "dct_counts", nch, &counts));
+        for (int64_t j = 0; j < nch; ++j)
+            HIPCHK(ctx, soft_dct_count(d, std::min(n, j * rc), std::min(n, (j + 1) * rc), colptr, xt_row, dw,
+                                       counts + j, s));
+        std::vector<int64_t> hc((size_t)nch);
+        HIPCHK(ctx, hipMemcpyAsync(hc.data(), counts, (size_t)nch * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        dw.max_pieces = 0;
+        for (int64_t j = 0; j < nch; ++j) dw.max_pieces = std::max(dw.max_pieces, hc[(size_t)j]);
+        STCHK(ws(ctx, "dct_item", std::max<int64_t>(dw.max_pieces, 1), &dw.item));
+        STCHK(ws(ctx, "dct_part", std::max<int64_t>(dw.max_pieces, 1) * (int64_t)k, &dw.part));
     }
     int first = 1;
     for (int64_t c0 = 0, j = 0; c0 < n || first; c0 += rc, ++j) {

@@ -742,20 +742,18 @@ hipError_t soft_csc(int64_t N, int64_t d, int64_t nnz, const int64_t* rp, const 
 //     block across all hot terms (k_dct_rowblock), so the workgroups of an
 //     XCD read the same block of dS rows at the same time and mostly from
 //     L2;
-//   * the rest: cut into pieces of `piece` entries (k_dct_piece).
+//   * the rest (mid terms): the same with blocks of mid_blk_rows rows.
 // Each piece is summed into a partial row, and k_dct_combine adds a term's
 // partial rows into dCT[t] in piece order.  Every sum has a fixed order, so
-// the result is run-to-run identical.  Bounds for sizing the partial rows: a
-// range of len > piece entries that is not hot has ceil(len / piece) <
-// 2 len / piece pieces, and a chunk with nnz_c nonzeros has at most
-// nnz_c / (hot_min + 1) hot terms of nblk pieces each.
+// the result is run-to-run identical.  The host counts every chunk's pieces
+// first (soft_dct_count) and sizes the partial rows for the largest.
 
 // lo/hi of every term's rows inside [c0, c1); np[t] = pieces of a long range
-// (else 0); hflag[t] = 1 for a hot term
+// (else 0); hflag / mflag mark the hot and the mid terms
 __global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, int64_t hot_min, int64_t nblk,
-                           const int64_t* __restrict__ colptr, const int32_t* __restrict__ xt_row,
+                           int64_t nblk_mid, const int64_t* __restrict__ colptr, const int32_t* __restrict__ xt_row,
                            int64_t* __restrict__ lo_out, int64_t* __restrict__ hi_out, int64_t* __restrict__ np,
-                           int64_t* __restrict__ hflag) {
+                           int64_t* __restrict__ hflag, int64_t* __restrict__ mflag) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= d) return;
     const int64_t b = colptr[t], e = colptr[t + 1];
@@ -783,15 +781,21 @@ __global__ void k_dct_plan(int64_t d, int64_t c0, int64_t c1, int64_t piece, int
     lo_out[t] = lo;
     hi_out[t] = hi;
     const int64_t n = hi - lo;
-    hflag[t] = n > hot_min ? 1 : 0;
-    np[t] = n > hot_min ? nblk : (n > piece ? (n + piece - 1) / piece : 0);
+    const bool is_hot = n > hot_min, is_mid = !is_hot && n > piece;
+    hflag[t] = is_hot ? 1 : 0;
+    mflag[t] = is_mid ? 1 : 0;
+    np[t] = is_hot ? nblk : (is_mid ? nblk_mid : 0);
 }
 
-// hot[hscan[t]] = t for the hot terms
-__global__ void k_dct_hot(int64_t d, const int64_t* __restrict__ hflag, const int64_t* __restrict__ hscan,
-                          int32_t* __restrict__ hot) {
+// list[scan[t]] = t for the flagged terms
+__global__ void k_dct_list(int64_t d, const int64_t* __restrict__ flag, const int64_t* __restrict__ scan,
+                           int32_t* __restrict__ list) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < d && hflag[t]) hot[hscan[t]] = (int32_t)t;
+    if (t < d && flag[t]) list[scan[t]] = (int32_t)t;
+}
+
+__global__ void k_dct_store_count(const int64_t* __restrict__ pstart, int64_t d, int64_t* __restrict__ count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count = pstart[d];
 }
 
 // first entry in [lo, hi) of the ascending xt_row whose row is >= r
@@ -927,43 +931,14 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_short(int64_t d, int32_t k,
     }
 }
 
-// one piece of a long range into its partial row, one column group per workgroup
-__global__ __launch_bounds__(kDctThreads) void k_dct_piece(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
-                                                           int64_t piece, int64_t hot_min,
-                                                           const int32_t* __restrict__ item,
-                                                           const int64_t* __restrict__ pstart,
-                                                           const int64_t* __restrict__ lo_t,
-                                                           const int64_t* __restrict__ hi_t,
-                                                           const int32_t* __restrict__ xt_row,
-                                                           const float* __restrict__ xt_val,
-                                                           const float* __restrict__ dS, float* __restrict__ part) {
-    const int x = blockIdx.x % kSoftGroups;
-    const int64_t kc = soft_group_width(k);
-    const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
-    const int64_t npieces = min(pstart[d], max_pieces);   // the host bound caps the device count
-    for (int64_t q = blockIdx.x / kSoftGroups; q < npieces; q += gridDim.x / kSoftGroups) {
-        const int32_t t = item[q];
-        if (hi_t[t] - lo_t[t] > hot_min) continue;   // a hot term: k_dct_rowblock
-        const int64_t j = q - pstart[t];
-        const int64_t p0 = lo_t[t] + j * piece, p1 = min(hi_t[t], p0 + piece);
-        for (int64_t cb = g0; cb < g1; cb += 4 * kDctThreads) {
-            const int64_t cq = cb + 4 * threadIdx.x;
-            if (cq >= g1) continue;
-            const bool vec = (k & 3) == 0 && cq + 4 <= g1;
-            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            dct_sum_g(k, c0, cq, g1, p0, p1, xt_row, xt_val, dS, acc);
-            store4_lim(part + q * (int64_t)k + cq, acc, cq, g1, vec);
-        }
-    }
-}
-
-// the hot terms' pieces, block by block: piece o covers row block o / H of
-// hot term o mod H (H hot terms), so concurrent workgroups read one block of
-// dS rows; one column group per workgroup
+// the pieces of a list of terms (the hot or the mid ones), block by block:
+// piece o covers row block o / H of term list[o mod H] (H = scan[d] terms), so
+// concurrent workgroups read one block of dS rows; one column group per
+// workgroup
 __global__ __launch_bounds__(kDctThreads) void k_dct_rowblock(int64_t d, int64_t max_pieces, int32_t k, int64_t c0,
                                                               int64_t c1, int64_t blk_rows, int64_t nblk,
-                                                              const int32_t* __restrict__ hot,
-                                                              const int64_t* __restrict__ hscan,
+                                                              const int32_t* __restrict__ list,
+                                                              const int64_t* __restrict__ scan,
                                                               const int64_t* __restrict__ pstart,
                                                               const int64_t* __restrict__ lo_t,
                                                               const int64_t* __restrict__ hi_t,
@@ -973,10 +948,10 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_rowblock(int64_t d, int64_t
     const int x = blockIdx.x % kSoftGroups;
     const int64_t kc = soft_group_width(k);
     const int64_t g0 = min((int64_t)k, x * kc), g1 = min((int64_t)k, g0 + kc);
-    const int64_t H = hscan[d];
+    const int64_t H = scan[d];
     for (int64_t o = blockIdx.x / kSoftGroups; o < H * nblk; o += gridDim.x / kSoftGroups) {
         const int64_t j = o / H;
-        const int32_t t = hot[o - j * H];
+        const int32_t t = list[o - j * H];
         const int64_t q = pstart[t] + j;
         if (q >= max_pieces) continue;   // cannot happen: the host bound holds
         const int64_t r0 = c0 + j * blk_rows, r1 = min(c1, r0 + blk_rows);
@@ -1036,32 +1011,53 @@ __global__ __launch_bounds__(kDctThreads) void k_dct_combine(int64_t d, int64_t 
     }
 }
 
+static hipError_t dct_plan(int64_t d, int64_t c0, int64_t c1, const int64_t* colptr, const int32_t* xt_row,
+                           const DctWs& w, hipStream_t s) {
+    const unsigned tb = (unsigned)((d + 255) / 256);
+    const int64_t nblk = (c1 - c0 + w.blk_rows - 1) / w.blk_rows;
+    const int64_t nblk_mid = (c1 - c0 + w.mid_blk_rows - 1) / w.mid_blk_rows;
+    hipLaunchKernelGGL(k_dct_plan, dim3(tb), dim3(256), 0, s, d, c0, c1, w.piece, w.hot_min, nblk, nblk_mid, colptr,
+                       xt_row, w.lo, w.hi, w.np, w.hflag, w.mflag);
+    hipError_t e = exclusive_scan_i64(w.np, w.pstart, d, w.scan_ws, s);
+    if (e == hipSuccess) e = exclusive_scan_i64(w.hflag, w.hscan, d, w.scan_ws, s);
+    if (e == hipSuccess) e = exclusive_scan_i64(w.mflag, w.mscan, d, w.scan_ws, s);
+    return e;
+}
+
+hipError_t soft_dct_count(int64_t d, int64_t c0, int64_t c1, const int64_t* colptr, const int32_t* xt_row, DctWs w,
+                          int64_t* count, hipStream_t s) {
+    if (d <= 0) return hipSuccess;
+    hipError_t e = dct_plan(d, c0, c1, colptr, xt_row, w, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dct_store_count, dim3(1), dim3(64), 0, s, w.pstart, d, count);
+    return hipGetLastError();
+}
+
 hipError_t soft_dct(int64_t d, int32_t k, int64_t c0, int64_t c1, int first, const int64_t* colptr,
                     const int32_t* xt_row, const float* xt_val, const float* dS, float* dCT, DctWs w, int n_cu,
                     hipStream_t s) {
     if (d <= 0) return hipSuccess;
     const unsigned tb = (unsigned)((d + 255) / 256);
-    const int64_t nblk = (c1 - c0 + w.blk_rows - 1) / w.blk_rows;
-    hipLaunchKernelGGL(k_dct_plan, dim3(tb), dim3(256), 0, s, d, c0, c1, w.piece, w.hot_min, nblk, colptr, xt_row, w.lo,
-                       w.hi, w.np, w.hflag);
-    hipError_t e = exclusive_scan_i64(w.np, w.pstart, d, w.scan_ws, s);
-    if (e != hipSuccess) return e;
-    e = exclusive_scan_i64(w.hflag, w.hscan, d, w.scan_ws, s);
+    hipError_t e = dct_plan(d, c0, c1, colptr, xt_row, w, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dct_items, dim3(tb), dim3(256), 0, s, d, w.max_pieces, w.np, w.pstart, w.item);
-    hipLaunchKernelGGL(k_dct_hot, dim3(tb), dim3(256), 0, s, d, w.hflag, w.hscan, w.hot);
+    hipLaunchKernelGGL(k_dct_list, dim3(tb), dim3(256), 0, s, d, w.hflag, w.hscan, w.hot);
+    hipLaunchKernelGGL(k_dct_list, dim3(tb), dim3(256), 0, s, d, w.mflag, w.mscan, w.mid);
     const int64_t grid = std::min<int64_t>(d, (int64_t)n_cu * 16) * kSoftGroups;
     hipLaunchKernelGGL(k_dct_short, dim3((unsigned)grid), dim3(kDctThreads), 0, s, d, k, c0, first, w.np, w.lo,
                        w.hi, xt_row, xt_val, dS, dCT);
-    // pieces: at most max_pieces (a bound from the chunk's nonzeros), the
+    // pieces: at most max_pieces (the host's count of the largest chunk), the
     // exact count is pstart[d] on the device
     if (w.max_pieces > 0) {
         const int64_t pg = std::min<int64_t>(w.max_pieces, (int64_t)n_cu * 16);
-        hipLaunchKernelGGL(k_dct_piece, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d, w.max_pieces, k,
-                           c0, w.piece, w.hot_min, w.item, w.pstart, w.lo, w.hi, xt_row, xt_val, dS, w.part);
+        const int64_t nblk = (c1 - c0 + w.blk_rows - 1) / w.blk_rows;
+        const int64_t nblk_mid = (c1 - c0 + w.mid_blk_rows - 1) / w.mid_blk_rows;
         hipLaunchKernelGGL(k_dct_rowblock, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d,
                            w.max_pieces, k, c0, c1, w.blk_rows, nblk, w.hot, w.hscan, w.pstart, w.lo, w.hi, xt_row,
                            xt_val, dS, w.part);
+        hipLaunchKernelGGL(k_dct_rowblock, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d,
+                           w.max_pieces, k, c0, c1, w.mid_blk_rows, nblk_mid, w.mid, w.mscan, w.pstart, w.lo, w.hi,
+                           xt_row, xt_val, dS, w.part);
         hipLaunchKernelGGL(k_dct_combine, dim3((unsigned)(pg * kSoftGroups)), dim3(kDctThreads), 0, s, d, w.max_pieces,
                            k, first, w.item, w.np, w.pstart, w.part, dCT);
     }

@@ -105,7 +105,7 @@ def test_soft_rows_on_both_sides_of_the_register_limit(k):
 def test_soft_hot_terms_cut_at_row_blocks(k):
     # 40 terms, 20 per row: at k = 16384 the dS chunks hold 4096 rows, and in
     # the first one 15 terms have more than 2048 entries (summed in 512-row
-    # blocks across terms), 25 have 257..2048 (256-entry pieces); the second
+    # blocks across terms), 25 have 257..2048 (2048-row blocks); the second
     # chunk (1904 rows) has none above 2048; k = 16383 takes the unaligned
     # gathers
     log("soft hot terms k=%d" % k)
