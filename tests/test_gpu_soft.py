@@ -39,7 +39,8 @@ def _ctx():
     return Context(0)
 
 
-@pytest.mark.parametrize("n,d,k", [(300, 500, 50), (257, 800, 5003), (1000, 3000, 4096), (4000, 1500, 20000)])
+@pytest.mark.parametrize("n,d,k", [(300, 500, 50), (257, 800, 5003), (1000, 3000, 4096), (4000, 1500, 20000),
+                                   (200, 400, 1), (200, 400, 3)])
 def test_soft_forward_backward_match_oracle(n, d, k):
     log("soft n=%d d=%d k=%d" % (n, d, k))
     c, C = _case(n, d, k, seed=n + k)
