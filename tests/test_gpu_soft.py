@@ -128,6 +128,33 @@ def test_soft_hot_terms_cut_at_row_blocks(k):
     assert torch.equal(again[0], dC) and torch.equal(again[1], dX)
 
 
+def test_soft_empty_rows():
+    # rows without terms have S = 0, so lse = log k, and add nothing to dC;
+    # empty rows first, last and in a run, in a chunk with ordinary rows
+    log("soft empty rows")
+    c = synth.make_corpus(300, 500, 20, 1.1, np.float32, seed=31)
+    empty = {0, 7, 100, 101, 102, 103, 104, 299}
+    cols, vals, rp = [], [], [0]
+    for i in range(c.n):
+        if i not in empty:
+            cols.append(c.col[c.row_ptr[i]:c.row_ptr[i + 1]])
+            vals.append(c.val[c.row_ptr[i]:c.row_ptr[i + 1]])
+        rp.append(rp[-1] + (0 if i in empty else int(c.row_ptr[i + 1] - c.row_ptr[i])))
+    e = synth.Corpus(c.n, c.d, np.array(rp, np.int64), np.concatenate(cols).astype(np.int32),
+                     np.concatenate(vals).astype(np.float32))
+    C = synth.dense_centroids(c, synth.init_ids(c.n, 40, 5), noise=1e-3, seed=9)
+    X, Cg = _dev(e, C)
+    ctx = _ctx()
+    lse, _ = ctx.soft_assign_fwd(X, Cg, TAU)
+    lse_ref = oracle.soft_forward(e, C.astype(np.float64), TAU)
+    np.testing.assert_allclose(lse.cpu().numpy(), lse_ref, rtol=0, atol=5e-4)
+    assert abs(float(lse[0]) - math.log(40)) < 1e-5
+    dC, dX = ctx.soft_assign_bwd(X, Cg, TAU, lse, 0.8)
+    dC_ref, dX_ref = oracle.soft_backward(e, C.astype(np.float64), TAU, 0.8, lse_ref)
+    np.testing.assert_allclose(dX.cpu().numpy(), dX_ref, rtol=2e-3, atol=1e-9)
+    np.testing.assert_allclose(dC.cpu().numpy(), dC_ref, rtol=2e-3, atol=1e-7)
+
+
 def test_soft_backward_is_deterministic_and_partial_outputs():
     c, C = _case(800, 1200, 300, seed=3)
     X, Cg = _dev(c, C)
