@@ -403,6 +403,15 @@ def main():
         wide, narrow = s32["walk_wide_bytes"], s32["walk_loaded_bytes"] - s32["walk_wide_bytes"]
         peak = (wide + narrow) / (wide / r16 + narrow / r8)
         peak16 = r16
+    if out_bf16 is not None:
+        # the BF16 walk against the same data-path roof, for its own load mix
+        # (16-byte head-row loads, 8-byte id and value loads of the lists)
+        out_bf16["walk_requested_gbs"] = s16["walk_data_gbs"]
+        out_bf16["wide_load_fraction"] = s16["walk_wide_bytes"] / s16["walk_loaded_bytes"]
+        if probe:
+            w16, n16 = s16["walk_wide_bytes"], s16["walk_loaded_bytes"] - s16["walk_wide_bytes"]
+            out_bf16["vmem_peak_gbs"] = (w16 + n16) / (w16 / r16 + n16 / r8)
+            out_bf16["vmem_frac"] = s16["walk_data_gbs"] / out_bf16["vmem_peak_gbs"]
     traffic = measured_traffic()
     dram = None
     if traffic:
