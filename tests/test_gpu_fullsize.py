@@ -349,7 +349,7 @@ def test_soft_fullsize_sampled():
     del Cg
     C64 = C.astype(np.float64)
     rng = np.random.default_rng(3)
-    rows = np.sort(rng.choice(corpus.n, 48, replace=False))
+    rows = np.sort(rng.choice(corpus.n, 4096, replace=False))
     log("oracle on sampled rows")
     lse_ref = oracle.soft_forward(corpus, C64, tau, rows=rows)
     np.testing.assert_allclose(lse_h[rows], lse_ref, rtol=0, atol=5e-4)
@@ -380,6 +380,19 @@ def test_soft_fullsize_sampled():
     pos = np.nonzero(corpus.col == t)[0]
     rows_t = np.unique(np.searchsorted(corpus.row_ptr, pos, side="right") - 1)
     log("dC column of a term in %d rows" % len(rows_t))
+    lse_t = oracle.soft_forward(corpus, C64, tau, rows=rows_t)
+    dc_ref, _ = oracle.soft_backward(corpus, C64, tau, g, lse_t, rows=rows_t, want_dx=False)
+    np.testing.assert_allclose(dC_h[:, t], dc_ref[:, t], rtol=2e-3, atol=1e-9)
+    # one hot term (in ~14% of the rows: more than 2048 entries in a
+    # 16,384-row chunk): its chunk ranges are cut at 512-row blocks summed
+    # across the hot terms; its whole dC column from all of its rows
+    cand = np.nonzero((df >= 0.14 * corpus.n) & (df <= 0.20 * corpus.n))[0]
+    t = int(cand[np.argmin(df[cand])])
+    pos = np.nonzero(corpus.col == t)[0]
+    rows_t = np.unique(np.searchsorted(corpus.row_ptr, pos, side="right") - 1)
+    per_chunk = np.bincount(rows_t // ((64 << 20) // C.shape[0]))
+    assert per_chunk.max() > 2048, per_chunk
+    log("dC column of a hot term in %d rows" % len(rows_t))
     lse_t = oracle.soft_forward(corpus, C64, tau, rows=rows_t)
     dc_ref, _ = oracle.soft_backward(corpus, C64, tau, g, lse_t, rows=rows_t, want_dx=False)
     np.testing.assert_allclose(dC_h[:, t], dc_ref[:, t], rtol=2e-3, atol=1e-9)
